@@ -1,0 +1,172 @@
+/*
+ * mica_dp.h -- C ABI of the MI355X (gfx950) library for the dynamic-programming
+ * phase of short-read alignment.
+ *
+ * What it computes (MICA paper, Methods, "Highly parallel dynamic
+ * programming"): reads that few-mismatch search could not place are aligned
+ * by DP "with indels" (architecture section) against a candidate region of
+ * the reference, with the affine gap model of three tables M, I and D
+ * holding the best score of an alignment ending in a Match, an Insert or a
+ * Delete.  Cell (i,j) of the table depends on (i-1,j-1), (i-1,j) and
+ * (i,j-1).  DP is used where indels and soft clipping are needed, hence two
+ * modes: semi-global (the whole read against any substring of the window)
+ * and local (both ends clipped, Smith-Waterman).
+ *
+ * Readings of what the paper leaves open (scores, boundaries, ties, CIGAR):
+ *   - scoring: s(x,y) = match if x == y else mismatch; a gap of length L
+ *     scores -(gap_open + L * gap_extend).
+ *   - recurrences, 1 <= i <= m (read), 1 <= j <= n (window):
+ *       D(i,j) = max(D(i,j-1) - e, H(i,j-1) - o - e)      (deletion)
+ *       I(i,j) = max(I(i-1,j) - e, H(i-1,j) - o - e)      (insertion)
+ *       H(i,j) = max(H(i-1,j-1) + s(q_i, r_j), D, I)  [and 0 when local]
+ *   - semi-global boundary: H(0,j) = 0; H(i,0) = -(o + i*e); local: 0.
+ *   - result cell: semi-global, the largest H(m,j) over 0 <= j <= n, ties to
+ *     the smallest j; local, the largest H over all cells and (0,0), ties to
+ *     the smallest j, then the smallest i.
+ *   - traceback priorities: stop at H = 0 (local) > diagonal > D > I, and in
+ *     a gap, opening it here beats extending it.
+ *   - coordinates are 0-based, half-open and window-relative; CIGAR words are
+ *     (length << 4) | op with M = 0, I = 1, D = 2 (BAM codes; no clipping ops:
+ *     clipping is given by the start and end coordinates).
+ *
+ * Sequences are 2-bit packed: base codes A=0 C=1 G=2 T=3, base k of a buffer
+ * at bits 2*(k % 16) of 32-bit word k / 16.  All positions and lengths are in
+ * bases.
+ *
+ * Errors: every call returns a mica_status_t.  Batch-level problems (null
+ * pointers, bad scoring or flags, sizes over the limits) return an error and
+ * enqueue nothing.  Problems of a single pair are reported in that pair's
+ * status word and the rest of the batch runs.  HIP failures return
+ * MICA_ERR_HIP; mica_last_error() gives the text.  No C++ exception crosses
+ * this interface.
+ */
+#ifndef MICA_DP_H
+#define MICA_DP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MICA_OK = 0,
+  MICA_ERR_INVALID_ARG = -1,
+  MICA_ERR_LIMIT = -2,
+  MICA_ERR_OUT_OF_MEMORY = -3,
+  MICA_ERR_HIP = -4,
+  MICA_ERR_BUSY = -5
+} mica_status_t;
+
+/* Scoring: match > 0 and mismatch <= 0 are scores; gap_open >= 0 and
+ * gap_extend >= 1 are penalties.  Limits: 1 <= match <= 4096,
+ * -4096 <= mismatch <= 0, 0 <= gap_open <= 4096, 1 <= gap_extend <= 4096. */
+typedef struct {
+  int32_t match, mismatch, gap_open, gap_extend;
+} mica_scoring_t;
+
+enum { MICA_MODE_SEMIGLOBAL = 0, MICA_MODE_LOCAL = 1 };
+
+/* flags of mica_dp_align_batch */
+enum {
+  MICA_OUT_START = 1u << 0,   /* write read_start and ref_start (runs the traceback) */
+  MICA_OUT_CIGAR = 1u << 1,   /* write cigar and n_cigar (implies MICA_OUT_START) */
+  MICA_FORCE_INT32 = 1u << 8, /* compute every pair with 32-bit scores */
+  MICA_PLAIN_LAUNCH = 1u << 9 /* one launch per length bucket instead of the persistent one */
+};
+
+/* per-pair status bits */
+enum {
+  MICA_ST_SATURATED = 1u << 0,   /* 16-bit scores saturated; the 32-bit re-run result is final */
+  MICA_ST_CIGAR_TRUNC = 1u << 1, /* n_cigar = -(runs needed); cigar holds the first cigar_cap runs */
+  MICA_ST_LEN_LIMIT = 1u << 2,   /* m or n outside [0, limit]: not computed, outputs zero */
+  MICA_ST_WIN_OOB = 1u << 3,     /* window not inside the reference: not computed */
+  MICA_ST_READ_OOB = 1u << 4     /* read not inside the read buffer: not computed */
+};
+
+#define MICA_MAX_READ_LEN 1024
+#define MICA_MAX_WIN_LEN 8192
+
+/* Library context: device workspace, plan table and launch cache for one
+ * GPU.  Not thread-safe: use one context per host thread.  Calls that share
+ * a context must be ordered on one stream (they share its workspace). */
+typedef struct mica_ctx *mica_ctx_t;
+
+/* Create a context on HIP device `hip_device`.  `workspace_bytes` caps the
+ * device scratch the context may hold (0 = a default of 8 GiB); scratch is
+ * allocated lazily and grown as batches need.  Writes the handle to *out. */
+mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t *out);
+
+/* Free the context and its device memory (synchronises the device). */
+mica_status_t mica_ctx_destroy(mica_ctx_t ctx);
+
+/* One batch of independent (read, window) pairs.  Every pointer is a device
+ * pointer owned by the caller; inputs must stay unchanged and outputs alive
+ * until the work enqueued on the stream has completed. */
+typedef struct {
+  /* reference: 2-bit packed, ref_len bases */
+  const uint32_t *ref2b;
+  uint64_t ref_len;
+  /* pair p aligns read p against ref[win_off[p], win_off[p] + win_len[p]) */
+  const uint64_t *win_off;
+  const int32_t *win_len;
+  /* reads: 2-bit packed, reads_len bases; read p is reads[read_off[p], +read_len[p]) */
+  const uint32_t *reads2b;
+  uint64_t reads_len;
+  const uint64_t *read_off;
+  const int32_t *read_len;
+  const uint8_t *mode; /* per pair MICA_MODE_*; NULL: every pair uses default_mode */
+  int32_t default_mode;
+  int64_t n_pairs;
+  /* host-side upper bounds of read_len and win_len over the batch; they size
+   * the scratch and choose the kernels.  A pair above them is computed
+   * correctly only if within the hard limits; it is never unsafe. */
+  int32_t max_read_len, max_win_len;
+  /* outputs (n_pairs entries each) */
+  int32_t *score, *read_end, *ref_end; /* always written */
+  int32_t *read_start, *ref_start;     /* required with MICA_OUT_START or MICA_OUT_CIGAR */
+  uint32_t *cigar;                     /* n_pairs * cigar_cap words, required with MICA_OUT_CIGAR */
+  int32_t cigar_cap;
+  int32_t *n_cigar; /* required with MICA_OUT_CIGAR */
+  uint32_t *status; /* always written */
+} mica_batch_t;
+
+/* Align every pair of `batch` (Methods, DP section; readings above).
+ * Enqueues all work on `stream` (a hipStream_t; NULL = the null stream) and
+ * returns without synchronising.  The result of every pair is exact: pairs
+ * computed with 16-bit scores whose values reach the saturation guard band
+ * are recomputed with 32-bit scores on the device (MICA_ST_SATURATED). */
+mica_status_t mica_dp_align_batch(mica_ctx_t ctx, const mica_batch_t *batch,
+                                  const mica_scoring_t *scoring, uint32_t flags, void *stream);
+
+/* Pack n_bases base codes (one byte each, values 0..3) from device memory
+ * `codes` into 2-bit words at device pointer `words` (ceil(n/16) words; the
+ * unused high bits of the last word are zero).  Async on `stream`. */
+mica_status_t mica_pack_2bit(const uint8_t *codes, int64_t n_bases, uint32_t *words, void *stream);
+
+/* Kernel plan for reads of length in [m_lo, m_hi]: `lanes` lanes per pair
+ * (16 or 64) and `rows` read rows per lane (1..16), lanes * rows >= m_hi.
+ * Lengths not covered keep the default plan.  Plans only change speed, never
+ * results. */
+mica_status_t mica_ctx_set_plan(mica_ctx_t ctx, int32_t m_lo, int32_t m_hi, int32_t lanes,
+                                int32_t rows);
+
+/* Counters of the last batch enqueued on ctx (synchronises `stream`). */
+typedef struct {
+  int64_t n_pairs;      /* pairs in the batch */
+  int64_t n_items;      /* work items taken by the fill kernels */
+  int64_t n_saturated;  /* pairs re-run with 32-bit scores */
+  int64_t n_waves;      /* resident waves of the persistent launch */
+  int64_t scratch_bytes;
+} mica_batch_stats_t;
+mica_status_t mica_ctx_last_stats(mica_ctx_t ctx, void *stream, mica_batch_stats_t *out);
+
+/* Text of the last non-OK status returned on this host thread. */
+const char *mica_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MICA_DP_H */

@@ -1,0 +1,104 @@
+"""ctypes declarations of the C ABI in include/mica_dp.h.
+
+The shared library is built in-tree (libmica_dp.so next to this file).  There
+is no fallback: importing the binding without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmica_dp.so")
+
+OK = 0
+STATUS_NAMES = {0: "MICA_OK", -1: "MICA_ERR_INVALID_ARG", -2: "MICA_ERR_LIMIT",
+                -3: "MICA_ERR_OUT_OF_MEMORY", -4: "MICA_ERR_HIP", -5: "MICA_ERR_BUSY"}
+
+MODE_SEMIGLOBAL = 0
+MODE_LOCAL = 1
+OUT_START = 1 << 0
+OUT_CIGAR = 1 << 1
+FORCE_INT32 = 1 << 8
+PLAIN_LAUNCH = 1 << 9
+
+ST_SATURATED = 1 << 0
+ST_CIGAR_TRUNC = 1 << 1
+ST_LEN_LIMIT = 1 << 2
+ST_WIN_OOB = 1 << 3
+ST_READ_OOB = 1 << 4
+
+MAX_READ_LEN = 1024
+MAX_WIN_LEN = 8192
+
+EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_pack_2bit",
+           "mica_ctx_set_plan", "mica_ctx_last_stats", "mica_last_error")
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("ref2b", ctypes.c_void_p), ("ref_len", ctypes.c_uint64),
+        ("win_off", ctypes.c_void_p), ("win_len", ctypes.c_void_p),
+        ("reads2b", ctypes.c_void_p), ("reads_len", ctypes.c_uint64),
+        ("read_off", ctypes.c_void_p), ("read_len", ctypes.c_void_p),
+        ("mode", ctypes.c_void_p), ("default_mode", ctypes.c_int32),
+        ("n_pairs", ctypes.c_int64),
+        ("max_read_len", ctypes.c_int32), ("max_win_len", ctypes.c_int32),
+        ("score", ctypes.c_void_p), ("read_end", ctypes.c_void_p), ("ref_end", ctypes.c_void_p),
+        ("read_start", ctypes.c_void_p), ("ref_start", ctypes.c_void_p),
+        ("cigar", ctypes.c_void_p), ("cigar_cap", ctypes.c_int32),
+        ("n_cigar", ctypes.c_void_p), ("status", ctypes.c_void_p),
+    ]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("n_items", ctypes.c_int64),
+                ("n_saturated", ctypes.c_int64), ("n_waves", ctypes.c_int64),
+                ("scratch_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load libmica_dp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmica_dp.so is not built (%s); run __graft_entry__.build() "
+                          "or python -m paper_1402_4876_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+    lib.mica_ctx_create.argtypes = [ctypes.c_int, sz, ctypes.POINTER(P)]
+    lib.mica_ctx_create.restype = ctypes.c_int
+    lib.mica_ctx_destroy.argtypes = [P]
+    lib.mica_ctx_destroy.restype = ctypes.c_int
+    lib.mica_dp_align_batch.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), u32, P]
+    lib.mica_dp_align_batch.restype = ctypes.c_int
+    lib.mica_pack_2bit.argtypes = [P, i64, P, P]
+    lib.mica_pack_2bit.restype = ctypes.c_int
+    lib.mica_ctx_set_plan.argtypes = [P, i32, i32, i32, i32]
+    lib.mica_ctx_set_plan.restype = ctypes.c_int
+    lib.mica_ctx_last_stats.argtypes = [P, P, ctypes.POINTER(BatchStats)]
+    lib.mica_ctx_last_stats.restype = ctypes.c_int
+    lib.mica_last_error.argtypes = []
+    lib.mica_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class MicaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def check(status):
+    if status != OK:
+        raise MicaError(status, load().mica_last_error().decode(errors="replace"))

@@ -1,0 +1,125 @@
+// Internal definitions shared by the device kernels and the host runtime of
+// the DP-phase library.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mica {
+
+constexpr int kMaxM = 1024;  // longest read (rows)
+constexpr int kMaxN = 8192;  // longest window (columns)
+
+// Kernel classes: class c < 16 runs 16 lanes per pair with c+1 read rows per
+// lane (reads up to 16*(c+1) bases); class 16 runs a whole wave (64 lanes)
+// with 16 rows per lane (reads up to 1024 bases).
+constexpr int kNumClasses = 17;
+__host__ __device__ constexpr int class_lanes(int c) { return c < 16 ? 16 : 64; }
+__host__ __device__ constexpr int class_rows(int c) { return c < 16 ? c + 1 : 16; }
+
+// Arithmetic kinds: packed 16-bit (two pairs per 32-bit register), packed
+// 16-bit with a run-time saturation check, and 32-bit.
+enum Kind : int { kK16 = 0, kK16Sat = 1, kK32 = 2 };
+constexpr int kNumKinds = 3;
+constexpr int kNumBuckets = kNumKinds * kNumClasses * 2;
+__host__ __device__ constexpr int bucket_id(int kind, int cls, int mode) {
+  return (kind * kNumClasses + cls) * 2 + mode;
+}
+__host__ __device__ constexpr int bucket_kind(int b) { return b / (2 * kNumClasses); }
+__host__ __device__ constexpr int bucket_class(int b) { return (b / 2) % kNumClasses; }
+__host__ __device__ constexpr int bucket_mode(int b) { return b & 1; }
+// pairs handled by one wave-sized work item
+__host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
+  return (kind == kK32 ? 1 : 2) * (64 / class_lanes(cls));
+}
+
+// The persistent kernel serves the packed 16-bit buckets of the 16-lane
+// classes (the bulk of short-read work); the other buckets run as plain
+// per-bucket launches after it.
+__host__ __device__ constexpr bool persistent_bucket(int b) {
+  return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16;
+}
+
+constexpr uint32_t kSkip = 0xFFFFFFFFu;
+
+// counters[] slots
+enum : int { kCtrQueueHead = 0, kCtrRerun = 1, kCtrItems = 2, kCtrRerunHead = 3, kNumCounters = 8 };
+
+// per-pair status bits (same values as the public header)
+constexpr uint32_t kStSaturated = 1u << 0;
+constexpr uint32_t kStCigarTrunc = 1u << 1;
+constexpr uint32_t kStLenLimit = 1u << 2;
+constexpr uint32_t kStWinOob = 1u << 3;
+constexpr uint32_t kStReadOob = 1u << 4;
+
+constexpr uint32_t kOutStart = 1u << 0;
+constexpr uint32_t kOutCigar = 1u << 1;
+constexpr uint32_t kForceInt32 = 1u << 8;
+
+// LDS per wave (32-bit words): a window-selector ring of 256 columns for each
+// of up to 4 lane groups, plus a reduction area.
+constexpr int kRing = 256;
+constexpr int kRingWords = 4 * kRing;
+constexpr int kRedWords = 64 * 2 * 4;
+constexpr int kLdsWaveWords = kRingWords + kRedWords;
+constexpr int kWavesPerBlock = 4;
+
+struct Params {
+  // batch (device pointers owned by the caller)
+  const uint32_t* ref2b;
+  uint64_t ref_len;
+  const uint64_t* win_off;
+  const int32_t* win_len;
+  const uint32_t* reads2b;
+  uint64_t reads_len;
+  const uint64_t* read_off;
+  const int32_t* read_len;
+  const uint8_t* mode;
+  int32_t default_mode;
+  int32_t max_m, max_n;
+  int64_t n_pairs;
+  int32_t* score;
+  int32_t* read_end;
+  int32_t* ref_end;
+  int32_t* read_start;
+  int32_t* ref_start;
+  uint32_t* cigar;
+  int32_t cigar_cap;
+  int32_t* n_cigar;
+  uint32_t* status;
+  int32_t sa, sb, so, se;  // match, mismatch, gap open, gap extend
+  uint32_t flags;
+  // workspace (device memory of the context)
+  uint32_t* bucket_of;         // [n_pairs]
+  uint32_t* sorted;            // [n_pairs] pair ids grouped by bucket
+  uint32_t* rerun;             // [n_pairs] pair ids to recompute with 32-bit scores
+  uint32_t* bcount;            // [kNumBuckets]
+  uint32_t* bstart;            // [kNumBuckets]
+  uint32_t* bfill;             // [kNumBuckets]
+  uint32_t* qstart;            // [kNumBuckets + 1] first item of each queue position
+  const uint32_t* qorder;      // [kNumBuckets] bucket served at each queue position
+  const uint8_t* class_of_m;   // [kMaxM + 1]
+  uint32_t* counters;          // [kNumCounters]
+  uint8_t* scratch;            // n_slots * slot_bytes
+  uint64_t slot_bytes;         // per resident wave: direction bits + CIGAR staging
+  uint64_t dir_bytes;          // direction-bit part of a slot
+  int32_t stage_stride;        // CIGAR staging words per pair
+  int32_t n_slots;             // resident waves the scratch is sized for
+  uint32_t n_persist_q;        // queue positions served by the persistent kernel
+};
+
+}  // namespace mica
+
+namespace mica {
+typedef void (*KernelFn)(const Params*);
+// Kernel entry points of the library, indexed for the host runtime.
+struct KernelTable {
+  KernelFn bucket[2][kNumBuckets];  // [with traceback][bucket]
+  KernelFn persistent[2];
+  KernelFn rerun[2];
+  KernelFn zero, plan, scan, scatter;
+  KernelTable();
+};
+const KernelTable& kernels();
+hipError_t launch_pack2bit(const uint8_t* codes, int64_t n, uint32_t* words, hipStream_t s);
+}  // namespace mica

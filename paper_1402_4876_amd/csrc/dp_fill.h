@@ -1,0 +1,684 @@
+// HIP kernels (gfx950) for batched affine-gap DP alignment of reads against
+// reference windows: the DP phase of MICA (Methods, "Highly parallel dynamic
+// programming").
+//
+// Mapping (a CDNA4 redesign of the paper's anti-diagonal fill):
+//  * A group of P lanes (16 or 64) aligns one pair per 16-bit half of each
+//    32-bit register (two pairs per group, packed int16 with saturating
+//    v_pk_* arithmetic), or one pair with 32-bit scores.
+//  * Lane k holds R consecutive read rows in registers.  Window columns stream
+//    through the lanes: at step t lane k computes column t-k+1 for its R rows
+//    top to bottom, so the cells a step computes lie on an anti-diagonal band
+//    and every dependency is either in-lane or one lane up one step earlier.
+//    The bottom row's T = H - o - e and I move one lane down per step by DPP
+//    (row_shr:1 for 16-lane groups, wave_shr:1 for 64).
+//  * The read occupies the bottom m of the P*R row slots; the slots above are
+//    dummy rows whose substitution score is -1.  With the top boundary H = 0
+//    they hold H = -d (d = depth), so the last dummy row is the read's row 0
+//    shifted by -D0 (D0 = number of dummy rows).  Every value below is the
+//    true value shifted by the constant -D0 (max and + commute with a shift);
+//    the local floor 0 becomes -D0.  Row m is always the last register of the
+//    last lane.
+//  * The substitution score is one v_perm_b32 lookup: selector bytes come from
+//    XOR of a per-row read code and a per-column window code, the table holds
+//    the match and mismatch scores; a dummy row's code selects 0xFF bytes (-1).
+//  * Per cell and per direction kind one sign bit is kept (diagonal / deletion
+//    wins, deletion / insertion extends); the bits of a lane's rows for one
+//    step form one 32-bit word per kind, stored to the wave's scratch slot.
+//    After the fill one lane per pair walks them back to the start cell and
+//    writes the CIGAR.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "dp_common.h"
+
+namespace mica {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 as_s(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
+__device__ __forceinline__ uint32_t as_u(s16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t as_u(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+__device__ __forceinline__ int clamp16(int v) { return v < -32768 ? -32768 : (v > 32767 ? 32767 : v); }
+__device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t x, uint32_t y) {
+  return (mask & x) | (~mask & y);
+}
+
+// Packed 16-bit scores: half h of every register belongs to pair h of the group.
+struct V16 {
+  static constexpr int kPairs = 2;
+  typedef uint32_t T;
+  static constexpr uint32_t kNeg = 0x80008000u;
+  static constexpr uint32_t kQDummy = 0xF0F0F0F0u;
+  __device__ static T add(T a, T b) { return as_u(__builtin_elementwise_add_sat(as_s(a), as_s(b))); }
+  __device__ static T sub(T a, T b) { return as_u(__builtin_elementwise_sub_sat(as_s(a), as_s(b))); }
+  __device__ static T vmax(T a, T b) { return as_u(__builtin_elementwise_max(as_s(a), as_s(b))); }
+  __device__ static T vmin(T a, T b) { return as_u(__builtin_elementwise_min(as_s(a), as_s(b))); }
+  __device__ static T max3(T a, T b, T c) { return vmax(vmax(a, b), c); }
+  // append the sign bit of each half of d at bits 0 and 16
+  __device__ static T push(T acc, T d) {
+    return (acc << 1) | as_u(__builtin_bit_cast(u16x2, d) >> (u16x2){15, 15});
+  }
+  // 0xFFFF in each half where d < 0
+  __device__ static T negmask(T d) { return as_u(as_s(d) >> (s16x2){15, 15}); }
+  __device__ static T make2(int lo, int hi) {
+    return (uint32_t)(uint16_t)clamp16(lo) | ((uint32_t)(uint16_t)clamp16(hi) << 16);
+  }
+  __device__ static T splat(int v) { return make2(v, v); }
+  __device__ static int get(T x, int h) { return (int)(int16_t)(uint16_t)(x >> (16 * h)); }
+  __device__ static uint32_t getu(T x, int h) { return (x >> (16 * h)) & 0xFFFFu; }
+  // selector byte pattern of a read base q in half h, and of a window base r
+  __device__ static uint32_t qcode(int q, int h) {
+    return ((uint32_t)(2 * q) | ((uint32_t)(2 * q + 1) << 8)) << (16 * h);
+  }
+  __device__ static uint32_t qdummy(int h) { return 0xF0F0u << (16 * h); }
+  __device__ static uint32_t rcode(int r, int h) { return ((uint32_t)r * 0x0202u) << (16 * h); }
+  static constexpr int kBitsPerHalf = 16;
+};
+
+// 32-bit scores, one pair per group.
+struct V32 {
+  static constexpr int kPairs = 1;
+  typedef int32_t T;
+  static constexpr int32_t kNeg = -(1 << 29);
+  __device__ static T add(T a, T b) { return a + b; }
+  __device__ static T sub(T a, T b) { return a - b; }
+  __device__ static T vmax(T a, T b) { return a > b ? a : b; }
+  __device__ static T vmin(T a, T b) { return a < b ? a : b; }
+  __device__ static T max3(T a, T b, T c) { return vmax(vmax(a, b), c); }
+  __device__ static T push(T acc, T d) {
+    return (T)__builtin_amdgcn_alignbit((uint32_t)acc, (uint32_t)d, 31);  // (acc << 1) | (d >> 31)
+  }
+  __device__ static T splat(int v) { return v; }
+  __device__ static int get(T x, int) { return x; }
+  // bytes: 2q, 2q+1 pick a 16-bit table entry, 8+q replicate its sign
+  __device__ static uint32_t qcode(int q, int) {
+    return (uint32_t)(2 * q) | ((uint32_t)(2 * q + 1) << 8) | ((uint32_t)(8 + q) << 16) |
+           ((uint32_t)(8 + q) << 24);
+  }
+  __device__ static uint32_t qdummy(int) { return 0xF0F0F0F0u; }
+  __device__ static uint32_t rcode(int r, int) { return (uint32_t)r * 0x01010202u; }
+  static constexpr int kBitsPerHalf = 32;
+};
+
+template <int P>
+__device__ __forceinline__ uint32_t shift_down(uint32_t src, uint32_t old) {
+  // value of the lane above; the first lane of each group keeps `old`
+  if constexpr (P == 16)
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x111, 0xF, 0xF, false);
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ int base_at(const uint32_t* __restrict__ seq, uint64_t pos) {
+  return (int)((seq[pos >> 4] >> (2 * (uint32_t)(pos & 15))) & 3u);
+}
+
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// One wave-sized work item: G = 64/P groups, each aligning kPairs pairs.
+template <class V, int P, int R, int MODE, bool DIR, bool SAT>
+__device__ __forceinline__ void process_item(const Params* __restrict__ prm,
+                                          const uint32_t* __restrict__ pairs, int npairs,
+                                          uint32_t* lds, uint8_t* slot) {
+  typedef typename V::T T;
+  constexpr int NP = V::kPairs;
+  constexpr int PR = P * R;
+  constexpr bool LOCAL = (MODE == 1);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / P;
+  const int k = lane % P;
+  const int sa = prm->sa, sb = prm->sb, so = prm->so, se = prm->se;
+  const int oe = so + se;
+  const uint32_t* __restrict__ ref2b = prm->ref2b;
+  const uint32_t* __restrict__ reads2b = prm->reads2b;
+
+  // ---- the pairs of this lane's group --------------------------------------
+  int pid[NP], m[NP], n[NP], d0[NP];
+  uint64_t woff[NP], roff[NP];
+#pragma unroll
+  for (int h = 0; h < NP; ++h) {
+    const int idx = g * NP + h;
+    pid[h] = -1;
+    m[h] = PR;
+    n[h] = 0;
+    woff[h] = 0;
+    roff[h] = 0;
+    if (idx < npairs) {
+      const int p = (int)pairs[idx];
+      pid[h] = p;
+      m[h] = prm->read_len[p];
+      n[h] = prm->win_len[p];
+      woff[h] = prm->win_off[p];
+      roff[h] = prm->read_off[p];
+    }
+    d0[h] = PR - m[h];
+  }
+  // column range of the item (uniform loop, scalar loads)
+  int nmin = 1 << 30, nmax = 0;
+  for (int s = 0; s < npairs; ++s) {
+    const int nn = prm->win_len[pairs[s]];
+    nmin = nn < nmin ? nn : nmin;
+    nmax = nn > nmax ? nn : nmax;
+  }
+
+  // ---- read profile: selector code per row register -------------------------
+  uint32_t Q[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int u = k * R + r;
+    uint32_t q = 0;
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+      if (u < d0[h] || pid[h] < 0) {
+        q |= V::qdummy(h);
+      } else {
+        q |= V::qcode(base_at(reads2b, roff[h] + (uint64_t)(u - d0[h])), h);
+      }
+    }
+    Q[r] = q;
+  }
+  const uint32_t tab_lo = ((uint32_t)sa & 0xFFFFu) | ((uint32_t)sb << 16);
+  const uint32_t tab_hi = ((uint32_t)sb & 0xFFFFu) | ((uint32_t)sb << 16);
+
+  // ---- column 0 ---------------------------------------------------------------
+  T H[R], Tt[R], D[R];
+  T bb[LOCAL ? R : 1], cc[LOCAL ? R : 1];
+  int hv[NP];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int u = k * R + r;
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+      if (u < d0[h]) {
+        hv[h] = -(u + 1);
+      } else {
+        const int i = u - d0[h] + 1;
+        hv[h] = (LOCAL ? 0 : -(so + i * se)) - d0[h];
+      }
+    }
+    if constexpr (NP == 2) {
+      H[r] = V::make2(hv[0], hv[1]);
+      Tt[r] = V::make2(hv[0] - oe, hv[1] - oe);
+    } else {
+      H[r] = (T)hv[0];
+      Tt[r] = (T)(hv[0] - oe);
+    }
+    D[r] = (T)V::kNeg;
+  }
+  T floor_v = (T)0;
+  if constexpr (LOCAL) {
+    if constexpr (NP == 2)
+      floor_v = V::make2(-d0[0], -d0[1]);
+    else
+      floor_v = (T)(-d0[0]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      bb[r] = floor_v;
+      cc[r] = (T)0;
+    }
+  }
+  T hmax = (T)0, tmin = (T)0;
+  if constexpr (SAT) {
+    hmax = V::splat(-32768);
+    tmin = V::splat(32767);
+#pragma unroll
+    for (int r = 0; r < R; ++r) tmin = V::vmin(tmin, Tt[r]);
+  }
+  // semi-global best over row m: key (score << 16 | 0xFFFF - j), or (score, j)
+  int32_t best_key[NP];
+  int32_t best_h32 = 0, best_j32 = 0;
+  if constexpr (!LOCAL) {
+    if constexpr (NP == 2) {
+      best_key[0] = (int32_t)((H[R - 1] << 16) | 0xFFFFu);
+      best_key[1] = (int32_t)((H[R - 1] & 0xFFFF0000u) | 0xFFFFu);
+    } else {
+      best_h32 = (int32_t)H[R - 1];
+      best_j32 = 0;
+    }
+  }
+
+  uint32_t* ring = lds + g * kRing;
+  uint32_t* red = lds + kRingWords + 64 * 2 * 3;  // final (score, i*, j*) per pair
+  uint32_t* cand = lds + kRingWords;              // per-lane local candidates
+  uint4* dir4 = reinterpret_cast<uint4*>(slot);
+
+  const T ev = V::splat(se);
+  const T oev = V::splat(oe);
+  const T tbound = V::splat(-oe);
+  const T negv = (T)V::kNeg;
+  T t_last = Tt[R - 1];
+  T i_last = negv;
+  T hdiag_next = (T)0;
+  T nn_v = (T)0;
+  if constexpr (NP == 2) nn_v = V::make2(n[0], n[1]);
+  const uint32_t kk16 = (uint32_t)k * 0x10001u;
+
+  auto fill_ring = [&](int c0) {
+    for (int x = k; x < kRing / 2; x += P) {
+      const int c = c0 + x;
+      uint32_t sel = 0;
+#pragma unroll
+      for (int h = 0; h < NP; ++h)
+        if (c < n[h]) sel |= V::rcode(base_at(ref2b, woff[h] + (uint64_t)c), h);
+      ring[c & (kRing - 1)] = sel;
+    }
+    lds_wait();
+  };
+
+  auto step = [&](int t, auto checks) {
+    constexpr bool CHECK = decltype(checks)::value;
+    if ((t & (kRing / 2 - 1)) == 0) fill_ring(t);
+    T tup = (T)shift_down<P>((uint32_t)t_last, (uint32_t)tbound);
+    T iup = (T)shift_down<P>((uint32_t)i_last, (uint32_t)negv);
+    T hdiag = hdiag_next;
+    hdiag_next = V::add(tup, oev);
+    const uint32_t rsel = ring[(t - k) & (kRing - 1)];
+    const int j = t - k + 1;
+    T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    if (!CHECK || j >= 1) {
+      T jj = (T)0, vmask = (T)0;
+      if constexpr (LOCAL) {
+        if constexpr (NP == 2) {
+          jj = (uint32_t)(t + 1) * 0x10001u - kk16;
+          if constexpr (CHECK) vmask = ~V::negmask(V::sub(nn_v, jj));
+        } else {
+          jj = (T)j;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const T s = (T)__builtin_amdgcn_perm(tab_hi, tab_lo, Q[r] ^ rsel);
+        const T x = V::add(hdiag, s);
+        const T dn = V::vmax(V::sub(D[r], ev), Tt[r]);
+        const T in = V::vmax(V::sub(iup, ev), tup);
+        T h = V::max3(x, dn, in);
+        if constexpr (LOCAL) h = V::vmax(h, floor_v);
+        const T tn = V::sub(h, oev);
+        if constexpr (DIR) {
+          acc0 = V::push(acc0, V::sub(x, h));      // 1: diagonal loses
+          acc1 = V::push(acc1, V::sub(dn, h));     // 1: deletion loses
+          acc2 = V::push(acc2, V::sub(Tt[r], dn)); // 1: deletion extends
+          acc3 = V::push(acc3, V::sub(tup, in));   // 1: insertion extends
+        }
+        if constexpr (LOCAL) {
+          if constexpr (NP == 2) {
+            uint32_t msk = V::negmask(V::sub(bb[r], h));
+            if constexpr (CHECK) msk &= vmask;
+            cc[r] = bfi(msk, jj, cc[r]);
+            bb[r] = bfi(msk, h, bb[r]);
+          } else {
+            const bool ok = (h > bb[r]) && (!CHECK || j <= n[0]);
+            bb[r] = ok ? h : bb[r];
+            cc[r] = ok ? jj : cc[r];
+          }
+        }
+        if constexpr (SAT) {
+          hmax = V::vmax(hmax, h);
+          tmin = V::vmin(tmin, tn);
+        }
+        hdiag = H[r];
+        H[r] = h;
+        Tt[r] = tn;
+        D[r] = dn;
+        tup = tn;
+        iup = in;
+      }
+      i_last = iup;
+    }
+    t_last = Tt[R - 1];
+    if constexpr (DIR) {
+      dir4[t * 64 + lane] = make_uint4((uint32_t)acc0, (uint32_t)acc1, (uint32_t)acc2, (uint32_t)acc3);
+    }
+    if constexpr (!LOCAL) {
+      // row m sits in the last register of the last lane: column t - P + 2
+      const int jl = t - P + 2;
+      if (jl >= 1) {
+        if constexpr (NP == 2) {
+          const uint32_t hm = (uint32_t)H[R - 1];
+          const uint32_t jk = 0xFFFFu - (uint32_t)jl;
+          int32_t k0 = (int32_t)((hm << 16) | jk);
+          int32_t k1 = (int32_t)((hm & 0xFFFF0000u) | jk);
+          if constexpr (CHECK) {
+            k0 = jl <= n[0] ? k0 : INT32_MIN;
+            k1 = jl <= n[1] ? k1 : INT32_MIN;
+          }
+          best_key[0] = k0 > best_key[0] ? k0 : best_key[0];
+          best_key[1] = k1 > best_key[1] ? k1 : best_key[1];
+        } else {
+          const int32_t hm = (int32_t)H[R - 1];
+          const bool ok = (hm > best_h32) && (!CHECK || jl <= n[0]);
+          best_h32 = ok ? hm : best_h32;
+          best_j32 = ok ? jl : best_j32;
+        }
+      }
+    }
+  };
+
+  const int t_end = nmax + P - 1;
+  int t = 0;
+  for (; t < (P - 1 < t_end ? P - 1 : t_end); ++t) step(t, std::true_type{});
+  for (; t < nmin; ++t) step(t, std::false_type{});
+  for (; t < t_end; ++t) step(t, std::true_type{});
+
+  // ---- result cell ------------------------------------------------------------
+  // red[(g*NP + h)*4 + {0,1,2}] = shifted score, i*, j*
+  if constexpr (!LOCAL) {
+    if (k == P - 1) {
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        int sc, jj;
+        if constexpr (NP == 2) {
+          sc = best_key[h] >> 16;
+          jj = 0xFFFF - (best_key[h] & 0xFFFF);
+        } else {
+          sc = best_h32;
+          jj = best_j32;
+        }
+        red[(g * NP + h) * 4 + 0] = (uint32_t)sc;
+        red[(g * NP + h) * 4 + 1] = (uint32_t)m[h];
+        red[(g * NP + h) * 4 + 2] = (uint32_t)jj;
+      }
+    }
+  } else {
+    // per lane: best over its real rows, order (score desc, j asc, i asc)
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+      int b0 = -d0[h], c0 = 0, i0 = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int u = k * R + r;
+        if (u >= d0[h]) {
+          int bv, cv;
+          if constexpr (NP == 2) {
+            bv = V::get(bb[r], h);
+            cv = (int)((uint32_t)cc[r] >> (16 * h) & 0xFFFFu);
+          } else {
+            bv = bb[r];
+            cv = cc[r];
+          }
+          const int iv = u - d0[h] + 1;
+          if (bv > b0 || (bv == b0 && (cv < c0 || (cv == c0 && iv < i0)))) {
+            b0 = bv;
+            c0 = cv;
+            i0 = iv;
+          }
+        }
+      }
+      cand[(lane * NP + h) * 3 + 0] = (uint32_t)b0;
+      cand[(lane * NP + h) * 3 + 1] = (uint32_t)c0;
+      cand[(lane * NP + h) * 3 + 2] = (uint32_t)i0;
+    }
+    lds_wait();
+    int fb[NP], fc[NP], fi[NP];
+    if (k == P - 1) {
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        int b0 = -d0[h], c0 = 0, i0 = 0;
+        for (int kk = 0; kk < P; ++kk) {
+          const int src = (g * P + kk) * NP + h;
+          const int bv = (int)cand[src * 3 + 0], cv = (int)cand[src * 3 + 1], iv = (int)cand[src * 3 + 2];
+          if (bv > b0 || (bv == b0 && (cv < c0 || (cv == c0 && iv < i0)))) {
+            b0 = bv;
+            c0 = cv;
+            i0 = iv;
+          }
+        }
+        fb[h] = b0;
+        fc[h] = c0;
+        fi[h] = i0;
+      }
+    }
+    lds_wait();
+    if (k == P - 1) {
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        red[(g * NP + h) * 4 + 0] = (uint32_t)fb[h];
+        red[(g * NP + h) * 4 + 1] = (uint32_t)fi[h];
+        red[(g * NP + h) * 4 + 2] = (uint32_t)fc[h];
+      }
+    }
+  }
+  // saturation: any lane of the group flags the pair
+  bool sat_h[NP];
+#pragma unroll
+  for (int h = 0; h < NP; ++h) sat_h[h] = false;
+  if constexpr (SAT) {
+    const int gd = (sa > -sb ? sa : -sb) > oe ? (sa > -sb ? sa : -sb) : oe;
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+      const bool mine = V::get(hmax, h) >= 32767 - gd || V::get(tmin, h) <= -32768 + gd;
+      const uint64_t bal = __ballot(mine);
+      uint64_t gm = ~0ull;
+      if constexpr (P < 64) gm = ((1ull << (P < 64 ? P : 0)) - 1) << (g * P);
+      sat_h[h] = (bal & gm) != 0;
+    }
+  }
+  lds_wait();
+  if constexpr (DIR) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+
+  // ---- outputs and traceback: lane k = h of each group handles pair h --------
+  if (k < NP) {
+    const int h = k;
+    int p_, m_, n_, d0_;
+    uint64_t wo_, ro_;
+    bool sat_;
+    if constexpr (NP == 2) {
+      p_ = h ? pid[1] : pid[0];
+      m_ = h ? m[1] : m[0];
+      n_ = h ? n[1] : n[0];
+      d0_ = h ? d0[1] : d0[0];
+      wo_ = h ? woff[1] : woff[0];
+      ro_ = h ? roff[1] : roff[0];
+      sat_ = h ? sat_h[1] : sat_h[0];
+    } else {
+      p_ = pid[0];
+      m_ = m[0];
+      n_ = n[0];
+      d0_ = d0[0];
+      wo_ = woff[0];
+      ro_ = roff[0];
+      sat_ = sat_h[0];
+    }
+    (void)n_;
+    if (p_ >= 0) {
+      if (sat_) {
+        const uint32_t pos = atomicAdd(&prm->counters[kCtrRerun], 1u);
+        prm->rerun[pos] = (uint32_t)p_;
+      } else {
+        const int score = (int)red[(g * NP + h) * 4 + 0] + d0_;
+        const int ie = (int)red[(g * NP + h) * 4 + 1];
+        const int je = (int)red[(g * NP + h) * 4 + 2];
+        prm->score[p_] = score;
+        prm->read_end[p_] = ie;
+        prm->ref_end[p_] = je;
+        uint32_t st = 0;
+        if constexpr (DIR) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          uint32_t* stg = reinterpret_cast<uint32_t*>(slot + prm->dir_bytes) +
+                          (size_t)(g * NP + h) * (size_t)prm->stage_stride;
+          int i = ie, j = je;
+          int hval = score;  // true H of the current cell (local zero test)
+          int state = 0;     // 0: H, 1: D, 2: I
+          int nruns = 0, cur_op = -1, cur_len = 0;
+          auto emit = [&](int op, int len) {
+            if (op == cur_op) {
+              cur_len += len;
+            } else {
+              if (cur_len > 0) stg[nruns++] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
+              cur_op = op;
+              cur_len = len;
+            }
+          };
+          for (;;) {
+            if (state == 0) {
+              if (LOCAL && hval == 0) break;
+              if (i == 0) break;
+              if (!LOCAL && j == 0) {
+                emit(1, i);
+                i = 0;
+                break;
+              }
+            }
+            const int u = d0_ + i - 1;
+            const int kk = u / R;
+            const int rr = u - kk * R;
+            const int ts = j + kk - 1;
+            const uint4 w = dir4[ts * 64 + g * P + kk];
+            const int bit = h * V::kBitsPerHalf + (R - 1 - rr);
+            if (state == 0) {
+              if (((w.x >> bit) & 1u) == 0) {
+                emit(0, 1);
+                if (LOCAL) {
+                  const int qb = base_at(reads2b, ro_ + (uint64_t)(i - 1));
+                  const int rb = base_at(ref2b, wo_ + (uint64_t)(j - 1));
+                  hval -= (qb == rb) ? sa : sb;
+                }
+                --i;
+                --j;
+              } else if (((w.y >> bit) & 1u) == 0) {
+                state = 1;
+              } else {
+                state = 2;
+              }
+            } else if (state == 1) {
+              emit(2, 1);
+              if ((w.z >> bit) & 1u) {
+                hval += se;
+              } else {
+                hval += oe;
+                state = 0;
+              }
+              --j;
+            } else {
+              emit(1, 1);
+              if ((w.w >> bit) & 1u) {
+                hval += se;
+              } else {
+                hval += oe;
+                state = 0;
+              }
+              --i;
+            }
+          }
+          if (cur_len > 0) stg[nruns++] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
+          if (prm->flags & (kOutStart | kOutCigar)) {
+            prm->read_start[p_] = i;
+            prm->ref_start[p_] = j;
+          }
+          if (prm->flags & kOutCigar) {
+            const int cap = prm->cigar_cap;
+            uint32_t* out = prm->cigar + (size_t)p_ * (size_t)cap;
+            const int ncopy = nruns < cap ? nruns : cap;
+            for (int x = 0; x < ncopy; ++x) out[x] = stg[nruns - 1 - x];
+            if (nruns > cap) {
+              st |= kStCigarTrunc;
+              prm->n_cigar[p_] = -nruns;
+            } else {
+              prm->n_cigar[p_] = nruns;
+            }
+          }
+        }
+        prm->status[p_] = st;
+      }
+    }
+  }
+  lds_wait();
+}
+
+// ----------------------------------------------------------------------------
+// dispatch of (kind, class, mode) to the specialised item function
+
+template <bool DIR, int CLS, int KIND, int MODE>
+__device__ __forceinline__ void run_one(const Params* prm, const uint32_t* pairs, int np,
+                                        uint32_t* lds, uint8_t* slot) {
+  constexpr int P = class_lanes(CLS);
+  constexpr int R = class_rows(CLS);
+  if constexpr (KIND == kK32)
+    process_item<V32, P, R, MODE, DIR, false>(prm, pairs, np, lds, slot);
+  else
+    process_item<V16, P, R, MODE, DIR, KIND == kK16Sat>(prm, pairs, np, lds, slot);
+}
+
+template <bool DIR, int CLS = 0>
+__device__ __forceinline__ void dispatch(int bucket, const Params* prm, const uint32_t* pairs, int np,
+                                         uint32_t* lds, uint8_t* slot) {
+  if constexpr (CLS < kNumClasses && class_lanes(CLS) == 16) {
+    if (bucket_class(bucket) == CLS) {
+      if (bucket_mode(bucket)) run_one<DIR, CLS, kK16, 1>(prm, pairs, np, lds, slot);
+      else run_one<DIR, CLS, kK16, 0>(prm, pairs, np, lds, slot);
+    } else {
+      dispatch<DIR, CLS + 1>(bucket, prm, pairs, np, lds, slot);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Persistent launch: every resident wave takes work items from one queue
+// (buckets in descending cost order) until it is empty.
+template <bool DIR>
+__global__ __launch_bounds__(256) void k_fill_persistent(const Params* __restrict__ prm) {
+  extern __shared__ uint32_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int slot_id = blockIdx.x * kWavesPerBlock + wave;
+  if (slot_id >= prm->n_slots) return;
+  uint32_t* lds = smem + wave * kLdsWaveWords;
+  uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
+  const uint32_t total = prm->qstart[prm->n_persist_q];
+  for (;;) {
+    uint32_t v = 0;
+    if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead], 1u);
+    const uint32_t item = wave_uniform(v);
+    if (item >= total) break;
+    // queue position: last q with qstart[q] <= item
+    int lo = 0, hi = (int)prm->n_persist_q - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prm->qstart[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const int bucket = (int)prm->qorder[lo];
+    const uint32_t idx = item - prm->qstart[lo];
+    const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
+    const uint32_t first = idx * (uint32_t)ppi;
+    const uint32_t cnt = prm->bcount[bucket];
+    const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
+    dispatch<DIR>(bucket, prm, prm->sorted + prm->bstart[bucket] + first, np, lds, slot);
+  }
+}
+
+// Plain launch: one bucket per kernel, waves stride over its items.
+template <bool DIR, int KIND, int CLS, int MODE>
+__global__ __launch_bounds__(256) void k_fill_bucket(const Params* __restrict__ prm) {
+  extern __shared__ uint32_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int slot_id = blockIdx.x * kWavesPerBlock + wave;
+  if (slot_id >= prm->n_slots) return;
+  uint32_t* lds = smem + wave * kLdsWaveWords;
+  uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
+  constexpr int bucket = bucket_id(KIND, CLS, MODE);
+  constexpr int ppi = pairs_per_item(KIND, CLS);
+  const uint32_t cnt = prm->bcount[bucket];
+  const uint32_t items = (cnt + ppi - 1) / ppi;
+  const uint32_t* base = prm->sorted + prm->bstart[bucket];
+  for (uint32_t it = (uint32_t)slot_id; it < items; it += (uint32_t)prm->n_slots) {
+    const uint32_t first = it * ppi;
+    const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
+    run_one<DIR, CLS, KIND, MODE>(prm, base + first, np, lds, slot);
+  }
+}
+
+template <bool DIR, int KIND, int MODE, int... CLS>
+void fill_bucket_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
+  ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_bucket<DIR, KIND, CLS, MODE>), ...);
+}
+using ClassSeq = std::make_integer_sequence<int, kNumClasses>;
+
+}  // namespace mica

@@ -1,0 +1,191 @@
+// Planning, bucketing, 2-bit packing and saturated-pair re-run kernels, and
+// the table of kernel entry points used by the host runtime.
+#include "dp_fill.h"
+
+namespace mica {
+
+// Exact 32-bit recomputation of the pairs whose 16-bit scores saturated.
+template <bool DIR>
+__global__ __launch_bounds__(256) void k_rerun(const Params* __restrict__ prm) {
+  extern __shared__ uint32_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int slot_id = blockIdx.x * kWavesPerBlock + wave;
+  if (slot_id >= prm->n_slots) return;
+  uint32_t* lds = smem + wave * kLdsWaveWords;
+  uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
+  const uint32_t cnt = prm->counters[kCtrRerun];
+  for (uint32_t it = (uint32_t)slot_id; it < cnt; it += (uint32_t)prm->n_slots) {
+    const uint32_t* pp = prm->rerun + it;
+    const int p = (int)*pp;
+    const int md = prm->mode ? prm->mode[p] : prm->default_mode;
+    if (md) process_item<V32, 64, 16, 1, DIR, false>(prm, pp, 1, lds, slot);
+    else process_item<V32, 64, 16, 0, DIR, false>(prm, pp, 1, lds, slot);
+    if ((threadIdx.x & 63) == 0) prm->status[p] |= kStSaturated;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// planning: validation, trivial pairs, bucket histogram, work queue
+
+__global__ void k_zero(const Params* __restrict__ prm) {
+  const int i = threadIdx.x;
+  if (i < kNumBuckets) {
+    prm->bcount[i] = 0;
+    prm->bfill[i] = 0;
+  }
+  if (i < kNumCounters) prm->counters[i] = 0;
+}
+
+__device__ __forceinline__ bool int16_safe(int m, int n, int mode, int d0, int a, int b, int o, int e) {
+  const long hi = (long)a * (long)(m < n ? m : n) - d0;
+  const long lo = (mode ? -(long)(o + e) : -(long)(2 * o + (long)(m + 1) * e)) - d0;
+  (void)b;
+  return hi <= 32767 - 8 && lo >= -32767 + 8;
+}
+
+__global__ __launch_bounds__(256) void k_plan(const Params* __restrict__ prm) {
+  __shared__ uint32_t hist[kNumBuckets];
+  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < prm->n_pairs) {
+    const int m = prm->read_len[p], n = prm->win_len[p];
+    const int md = prm->mode ? (int)prm->mode[p] : prm->default_mode;
+    const uint64_t wo = prm->win_off[p], ro = prm->read_off[p];
+    uint32_t st = 0;
+    if (m < 0 || n < 0 || m > prm->max_m || n > prm->max_n) st = kStLenLimit;
+    else if (wo > prm->ref_len || (uint64_t)n > prm->ref_len - wo) st = kStWinOob;
+    else if (ro > prm->reads_len || (uint64_t)m > prm->reads_len - ro) st = kStReadOob;
+    else if (md != 0 && md != 1) st = kStLenLimit;
+    const bool want_start = (prm->flags & (kOutStart | kOutCigar)) != 0;
+    const bool want_cigar = (prm->flags & kOutCigar) != 0;
+    uint32_t b = kSkip;
+    if (st != 0 || m == 0 || n == 0) {
+      int score = 0, re = 0;
+      int ncig = 0;
+      if (st == 0 && md == 0 && m > 0) {  // semi-global against an empty window
+        score = -(prm->so + m * prm->se);
+        re = m;
+        ncig = 1;
+        if (want_cigar) {
+          if (prm->cigar_cap >= 1) prm->cigar[(size_t)p * prm->cigar_cap] = ((uint32_t)m << 4) | 1u;
+          else st |= kStCigarTrunc;
+        }
+      }
+      prm->score[p] = score;
+      prm->read_end[p] = re;
+      prm->ref_end[p] = 0;
+      if (want_start) {
+        prm->read_start[p] = 0;
+        prm->ref_start[p] = 0;
+      }
+      if (want_cigar) prm->n_cigar[p] = (st & kStCigarTrunc) ? -ncig : ncig;
+      prm->status[p] = st;
+    } else {
+      const int cls = prm->class_of_m[m];
+      const int d0 = class_lanes(cls) * class_rows(cls) - m;
+      int kind;
+      if (prm->flags & kForceInt32) kind = kK32;
+      else kind = int16_safe(m, n, md, d0, prm->sa, prm->sb, prm->so, prm->se) ? kK16 : kK16Sat;
+      b = (uint32_t)bucket_id(kind, cls, md);
+      atomicAdd(&hist[b], 1u);
+    }
+    prm->bucket_of[p] = b;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x)
+    if (hist[i]) atomicAdd(&prm->bcount[i], hist[i]);
+}
+
+__global__ void k_scan(const Params* __restrict__ prm) {
+  if (threadIdx.x != 0) return;
+  uint32_t acc = 0;
+  for (int b = 0; b < kNumBuckets; ++b) {
+    prm->bstart[b] = acc;
+    acc += prm->bcount[b];
+  }
+  uint32_t items = 0;
+  for (int q = 0; q < kNumBuckets; ++q) {
+    const int b = (int)prm->qorder[q];
+    prm->qstart[q] = items;
+    const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), bucket_class(b));
+    items += (prm->bcount[b] + ppi - 1) / ppi;
+  }
+  prm->qstart[kNumBuckets] = items;
+  prm->counters[kCtrItems] = items;
+  prm->counters[kCtrQueueHead] = 0;
+  prm->counters[kCtrRerun] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const Params* __restrict__ prm) {
+  __shared__ uint32_t cnt[kNumBuckets];
+  __shared__ uint32_t base[kNumBuckets];
+  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t b = kSkip, rank = 0;
+  if (p < prm->n_pairs) {
+    b = prm->bucket_of[p];
+    if (b != kSkip) rank = atomicAdd(&cnt[b], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x)
+    base[i] = cnt[i] ? atomicAdd(&prm->bfill[i], cnt[i]) : 0;
+  __syncthreads();
+  if (b != kSkip) prm->sorted[prm->bstart[b] + base[b] + rank] = (uint32_t)p;
+}
+
+__global__ __launch_bounds__(256) void k_pack2bit(const uint8_t* __restrict__ codes, int64_t n,
+                                                   uint32_t* __restrict__ words) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nw = (n + 15) / 16;
+  if (w >= nw) return;
+  uint32_t v = 0;
+  const int64_t b0 = w * 16;
+  for (int x = 0; x < 16; ++x) {
+    const int64_t i = b0 + x;
+    if (i < n) v |= ((uint32_t)codes[i] & 3u) << (2 * x);
+  }
+  words[w] = v;
+}
+
+}  // namespace mica
+
+namespace mica {
+
+// registration functions of the per-bucket fill kernels (one source file each)
+#define MICA_FILL_DECL(kind, mode, dir) void reg_fill_##kind##_##mode##_##dir(KernelTable& t);
+#define MICA_FILL_ALL(X) \
+  X(k16, 0, 0) X(k16, 0, 1) X(k16, 1, 0) X(k16, 1, 1) \
+  X(k16s, 0, 0) X(k16s, 0, 1) X(k16s, 1, 0) X(k16s, 1, 1) \
+  X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1)
+MICA_FILL_ALL(MICA_FILL_DECL)
+void reg_persistent_0(KernelTable& t);
+void reg_persistent_1(KernelTable& t);
+
+KernelTable::KernelTable() {
+#define MICA_FILL_CALL(kind, mode, dir) reg_fill_##kind##_##mode##_##dir(*this);
+  MICA_FILL_ALL(MICA_FILL_CALL)
+  reg_persistent_0(*this);
+  reg_persistent_1(*this);
+  rerun[0] = &k_rerun<false>;
+  rerun[1] = &k_rerun<true>;
+  zero = &k_zero;
+  plan = &k_plan;
+  scan = &k_scan;
+  scatter = &k_scatter;
+}
+
+const KernelTable& kernels() {
+  static KernelTable t;
+  return t;
+}
+
+hipError_t launch_pack2bit(const uint8_t* codes, int64_t n, uint32_t* words, hipStream_t s) {
+  const int64_t nw = (n + 15) / 16;
+  if (nw == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack2bit, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, codes, n, words);
+  return hipGetLastError();
+}
+
+}  // namespace mica

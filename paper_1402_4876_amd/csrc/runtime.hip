@@ -1,0 +1,375 @@
+// Host runtime of the DP-phase library: context, argument validation, device
+// workspace, kernel plan table and the launch sequence behind the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "dp_common.h"
+#include "mica_dp.h"
+
+using namespace mica;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mica_status_t fail(mica_status_t st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(MICA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+constexpr int kParamRing = 32;
+constexpr size_t kDefaultWorkspace = size_t(8) << 30;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct mica_ctx {
+  int device = 0;
+  size_t ws_cap = kDefaultWorkspace;
+  int n_cu = 256;
+  int occ_blocks[2] = {1, 1};  // resident blocks per CU of the persistent kernel
+  // device memory
+  Params* d_params = nullptr;     // ring of kParamRing parameter blocks
+  uint32_t* d_small = nullptr;    // bucket tables and counters
+  uint8_t* d_class = nullptr;     // class_of_m
+  uint32_t* d_pairs = nullptr;    // bucket_of | sorted | rerun
+  int64_t pair_cap = 0;
+  uint8_t* d_scratch = nullptr;
+  size_t scratch_cap = 0;
+  // host state
+  Params* h_params = nullptr;     // pinned ring
+  hipEvent_t ev[kParamRing] = {};
+  bool ev_used[kParamRing] = {};
+  int ring_pos = 0;
+  uint8_t class_of_m[kMaxM + 1];
+  uint32_t qorder[kNumBuckets];
+  uint32_t n_persist_q = 0;
+  bool class_dirty = true;
+  // last batch
+  int64_t last_pairs = 0;
+  int last_slots = 0;
+  size_t last_scratch = 0;
+};
+
+namespace {
+
+uint32_t* small_bcount(mica_ctx* c) { return c->d_small; }
+uint32_t* small_bstart(mica_ctx* c) { return c->d_small + kNumBuckets; }
+uint32_t* small_bfill(mica_ctx* c) { return c->d_small + 2 * kNumBuckets; }
+uint32_t* small_qstart(mica_ctx* c) { return c->d_small + 3 * kNumBuckets; }         // +1 entry
+uint32_t* small_qorder(mica_ctx* c) { return c->d_small + 4 * kNumBuckets + 8; }
+uint32_t* small_counters(mica_ctx* c) { return c->d_small + 5 * kNumBuckets + 8; }
+constexpr size_t kSmallWords = 5 * kNumBuckets + 8 + kNumCounters;
+
+// cost of one work item of a bucket, for the descending work-queue order
+double bucket_cost(int b) {
+  const int kind = bucket_kind(b), cls = bucket_class(b), mode = bucket_mode(b);
+  double c = class_rows(cls) * (class_lanes(cls) == 64 ? 1.5 : 1.0);
+  if (mode == 1) c *= 1.25;
+  if (kind == kK16Sat) c *= 1.1;
+  if (kind == kK32) c *= 1.05;
+  return c;
+}
+
+void default_plan(mica_ctx* c) {
+  for (int m = 0; m <= kMaxM; ++m) {
+    if (m <= 256) c->class_of_m[m] = (uint8_t)(m == 0 ? 0 : (m + 15) / 16 - 1);
+    else c->class_of_m[m] = 16;
+  }
+  c->class_dirty = true;
+}
+
+// same bound as the device planner: can every cell stay inside int16?
+bool int16_always_safe(int max_m, int max_n, const mica_scoring_t& s, bool any_local, bool any_sg) {
+  const long hi = (long)s.match * (long)std::min(max_m, max_n);
+  long lo = 0;
+  if (any_sg) lo = std::min(lo, -(long)(2 * s.gap_open + (long)(max_m + 1) * s.gap_extend) - (kMaxM - 1));
+  if (any_local) lo = std::min(lo, -(long)(s.gap_open + s.gap_extend) - (kMaxM - 1));
+  return hi <= 32767 - 8 && lo >= -32767 + 8;
+}
+
+mica_status_t ensure_pairs(mica_ctx* c, int64_t n) {
+  if (n <= c->pair_cap) return MICA_OK;
+  if (c->d_pairs) HIP_TRY(hipFree(c->d_pairs));
+  c->d_pairs = nullptr;
+  const int64_t cap = std::max<int64_t>(n, 1024);
+  if (hipMalloc(&c->d_pairs, (size_t)cap * 3 * sizeof(uint32_t)) != hipSuccess) {
+    c->pair_cap = 0;
+    return fail(MICA_ERR_OUT_OF_MEMORY, "cannot allocate per-pair workspace");
+  }
+  c->pair_cap = cap;
+  return MICA_OK;
+}
+
+mica_status_t ensure_scratch(mica_ctx* c, size_t bytes) {
+  if (bytes <= c->scratch_cap) return MICA_OK;
+  if (c->d_scratch) HIP_TRY(hipFree(c->d_scratch));
+  c->d_scratch = nullptr;
+  if (hipMalloc(&c->d_scratch, bytes) != hipSuccess) {
+    c->scratch_cap = 0;
+    return fail(MICA_ERR_OUT_OF_MEMORY, "cannot allocate traceback scratch");
+  }
+  c->scratch_cap = bytes;
+  return MICA_OK;
+}
+
+hipError_t launch(KernelFn fn, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
+                  const Params* dp) {
+  void* args[] = {(void*)&dp};
+  return hipLaunchKernel((const void*)fn, dim3(blocks), dim3(threads), args, shmem, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mica_last_error(void) { return g_last_error.c_str(); }
+
+mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t* out) {
+  if (!out) return fail(MICA_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (hip_device < 0 || hip_device >= ndev) return fail(MICA_ERR_INVALID_ARG, "no such HIP device");
+  HIP_TRY(hipSetDevice(hip_device));
+  mica_ctx* c = new mica_ctx();
+  c->device = hip_device;
+  if (workspace_bytes) c->ws_cap = workspace_bytes;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+  c->n_cu = prop.multiProcessorCount;
+  const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
+  for (int d = 0; d < 2; ++d) {
+    int nb = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kernels().persistent[d], 256, shmem));
+    c->occ_blocks[d] = std::max(nb, 1);
+  }
+  HIP_TRY(hipMalloc(&c->d_params, sizeof(Params) * kParamRing));
+  HIP_TRY(hipMalloc(&c->d_small, kSmallWords * sizeof(uint32_t)));
+  HIP_TRY(hipMalloc(&c->d_class, kMaxM + 1));
+  HIP_TRY(hipHostMalloc((void**)&c->h_params, sizeof(Params) * kParamRing, hipHostMallocDefault));
+  for (int i = 0; i < kParamRing; ++i) HIP_TRY(hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming));
+  default_plan(c);
+  // queue order: buckets by descending item cost
+  int order[kNumBuckets];
+  for (int b = 0; b < kNumBuckets; ++b) order[b] = b;
+  // buckets of the persistent kernel first, each part by descending item cost
+  std::stable_sort(order, order + kNumBuckets, [](int x, int y) {
+    if (persistent_bucket(x) != persistent_bucket(y)) return persistent_bucket(x);
+    return bucket_cost(x) > bucket_cost(y);
+  });
+  for (int b = 0; b < kNumBuckets; ++b) c->n_persist_q += persistent_bucket(b) ? 1 : 0;
+  for (int q = 0; q < kNumBuckets; ++q) c->qorder[q] = (uint32_t)order[q];
+  HIP_TRY(hipMemcpy(small_qorder(c), c->qorder, sizeof(c->qorder), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_class, c->class_of_m, kMaxM + 1, hipMemcpyHostToDevice));
+  c->class_dirty = false;
+  *out = c;
+  return MICA_OK;
+}
+
+mica_status_t mica_ctx_destroy(mica_ctx_t c) {
+  if (!c) return MICA_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (int i = 0; i < kParamRing; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->h_params) (void)hipHostFree(c->h_params);
+  if (c->d_params) (void)hipFree(c->d_params);
+  if (c->d_small) (void)hipFree(c->d_small);
+  if (c->d_class) (void)hipFree(c->d_class);
+  if (c->d_pairs) (void)hipFree(c->d_pairs);
+  if (c->d_scratch) (void)hipFree(c->d_scratch);
+  delete c;
+  return MICA_OK;
+}
+
+mica_status_t mica_ctx_set_plan(mica_ctx_t c, int32_t m_lo, int32_t m_hi, int32_t lanes, int32_t rows) {
+  if (!c) return fail(MICA_ERR_INVALID_ARG, "ctx is NULL");
+  if (m_lo < 1 || m_hi > kMaxM || m_lo > m_hi) return fail(MICA_ERR_INVALID_ARG, "bad read-length range");
+  int cls;
+  if (lanes == 16 && rows >= 1 && rows <= 16) cls = rows - 1;
+  else if (lanes == 64 && rows == 16) cls = 16;
+  else return fail(MICA_ERR_INVALID_ARG, "unsupported (lanes, rows)");
+  if (lanes * rows < m_hi) return fail(MICA_ERR_INVALID_ARG, "lanes * rows must cover m_hi");
+  for (int m = m_lo; m <= m_hi; ++m) c->class_of_m[m] = (uint8_t)cls;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpy(c->d_class, c->class_of_m, kMaxM + 1, hipMemcpyHostToDevice));
+  return MICA_OK;
+}
+
+mica_status_t mica_pack_2bit(const uint8_t* codes, int64_t n_bases, uint32_t* words, void* stream) {
+  if (n_bases < 0) return fail(MICA_ERR_INVALID_ARG, "n_bases < 0");
+  if (n_bases > 0 && (!codes || !words)) return fail(MICA_ERR_INVALID_ARG, "NULL pointer");
+  HIP_TRY(launch_pack2bit(codes, n_bases, words, (hipStream_t)stream));
+  return MICA_OK;
+}
+
+mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mica_scoring_t* s,
+                                  uint32_t flags, void* stream_) {
+  if (!c || !b || !s) return fail(MICA_ERR_INVALID_ARG, "NULL ctx, batch or scoring");
+  const uint32_t known = MICA_OUT_START | MICA_OUT_CIGAR | MICA_FORCE_INT32 | MICA_PLAIN_LAUNCH;
+  if (flags & ~known) return fail(MICA_ERR_INVALID_ARG, "unknown flag bits");
+  if (s->match < 1 || s->match > 4096 || s->mismatch > 0 || s->mismatch < -4096 || s->gap_open < 0 ||
+      s->gap_open > 4096 || s->gap_extend < 1 || s->gap_extend > 4096)
+    return fail(MICA_ERR_INVALID_ARG, "scoring outside its limits");
+  if (b->n_pairs < 0) return fail(MICA_ERR_INVALID_ARG, "n_pairs < 0");
+  if (b->n_pairs > 0xFFFFFFF0ll) return fail(MICA_ERR_LIMIT, "too many pairs in one batch");
+  if (b->default_mode != 0 && b->default_mode != 1) return fail(MICA_ERR_INVALID_ARG, "bad default_mode");
+  if (b->max_read_len < 0 || b->max_read_len > kMaxM || b->max_win_len < 0 || b->max_win_len > kMaxN)
+    return fail(MICA_ERR_LIMIT, "max_read_len / max_win_len beyond the library limits");
+  const bool want_cigar = flags & MICA_OUT_CIGAR;
+  const bool want_start = want_cigar || (flags & MICA_OUT_START);
+  if (b->n_pairs == 0) return MICA_OK;
+  if (!b->ref2b || !b->win_off || !b->win_len || !b->reads2b || !b->read_off || !b->read_len ||
+      !b->score || !b->read_end || !b->ref_end || !b->status)
+    return fail(MICA_ERR_INVALID_ARG, "NULL input or output pointer");
+  if (want_start && (!b->read_start || !b->ref_start))
+    return fail(MICA_ERR_INVALID_ARG, "read_start / ref_start required for start or CIGAR output");
+  if (want_cigar && (!b->n_cigar || b->cigar_cap < 0 || (b->cigar_cap > 0 && !b->cigar)))
+    return fail(MICA_ERR_INVALID_ARG, "cigar / n_cigar / cigar_cap invalid");
+  hipStream_t stream = (hipStream_t)stream_;
+  HIP_TRY(hipSetDevice(c->device));
+
+  mica_status_t st = ensure_pairs(c, b->n_pairs);
+  if (st != MICA_OK) return st;
+
+  // scratch: direction bits of a wave (steps x 64 lanes x 16 B) + CIGAR staging
+  const int max_m = b->max_read_len, max_n = b->max_win_len;
+  const size_t dir_bytes = want_start ? (size_t)(max_n + 64) * 64 * 16 : 0;
+  const int stage_stride = max_m + max_n + 2;
+  const size_t stage_bytes = want_start ? (size_t)8 * stage_stride * 4 : 0;
+  const size_t slot_bytes = std::max<size_t>(align_up(dir_bytes + stage_bytes, 256), 256);
+  const int d = want_start ? 1 : 0;
+  int64_t slots = (int64_t)c->occ_blocks[d] * c->n_cu * kWavesPerBlock;
+  const int64_t by_ws = (int64_t)(c->ws_cap / slot_bytes);
+  slots = std::min(slots, by_ws);
+  const int64_t need = (b->n_pairs + 1) / 2 + 3;  // upper bound of work items
+  slots = std::min(slots, need);
+  slots = std::max<int64_t>(align_up((size_t)std::max<int64_t>(slots, 1), kWavesPerBlock), kWavesPerBlock);
+  if ((size_t)slots * slot_bytes > c->ws_cap && slots > kWavesPerBlock)
+    slots = (int64_t)(c->ws_cap / slot_bytes) / kWavesPerBlock * kWavesPerBlock;
+  if (slots < kWavesPerBlock) return fail(MICA_ERR_OUT_OF_MEMORY, "workspace too small for one block");
+  st = ensure_scratch(c, (size_t)slots * slot_bytes);
+  if (st != MICA_OK) return st;
+
+  // parameter block (pinned ring slot, copied on the stream)
+  const int rp = c->ring_pos;
+  c->ring_pos = (c->ring_pos + 1) % kParamRing;
+  if (c->ev_used[rp]) HIP_TRY(hipEventSynchronize(c->ev[rp]));
+  Params& P = c->h_params[rp];
+  std::memset(&P, 0, sizeof(P));
+  P.ref2b = b->ref2b;
+  P.ref_len = b->ref_len;
+  P.win_off = b->win_off;
+  P.win_len = b->win_len;
+  P.reads2b = b->reads2b;
+  P.reads_len = b->reads_len;
+  P.read_off = b->read_off;
+  P.read_len = b->read_len;
+  P.mode = b->mode;
+  P.default_mode = b->default_mode;
+  P.max_m = max_m;
+  P.max_n = max_n;
+  P.n_pairs = b->n_pairs;
+  P.score = b->score;
+  P.read_end = b->read_end;
+  P.ref_end = b->ref_end;
+  P.read_start = want_start ? b->read_start : nullptr;
+  P.ref_start = want_start ? b->ref_start : nullptr;
+  P.cigar = want_cigar ? b->cigar : nullptr;
+  P.cigar_cap = want_cigar ? b->cigar_cap : 0;
+  P.n_cigar = want_cigar ? b->n_cigar : nullptr;
+  P.status = b->status;
+  P.sa = s->match;
+  P.sb = s->mismatch;
+  P.so = s->gap_open;
+  P.se = s->gap_extend;
+  P.flags = (want_start ? kOutStart : 0u) | (want_cigar ? kOutCigar : 0u) |
+            ((flags & MICA_FORCE_INT32) ? kForceInt32 : 0u);
+  P.bucket_of = c->d_pairs;
+  P.sorted = c->d_pairs + c->pair_cap;
+  P.rerun = c->d_pairs + 2 * c->pair_cap;
+  P.bcount = small_bcount(c);
+  P.bstart = small_bstart(c);
+  P.bfill = small_bfill(c);
+  P.qstart = small_qstart(c);
+  P.qorder = small_qorder(c);
+  P.class_of_m = c->d_class;
+  P.counters = small_counters(c);
+  P.scratch = c->d_scratch;
+  P.slot_bytes = slot_bytes;
+  P.dir_bytes = dir_bytes;
+  P.stage_stride = stage_stride;
+  P.n_slots = (int32_t)slots;
+  P.n_persist_q = c->n_persist_q;
+  Params* dp = c->d_params + rp;
+  HIP_TRY(hipMemcpyAsync(dp, &P, sizeof(Params), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(c->ev[rp], stream));
+  c->ev_used[rp] = true;
+
+  const KernelTable& K = kernels();
+  const unsigned pblocks = (unsigned)((b->n_pairs + 255) / 256);
+  const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
+  const unsigned fblocks = (unsigned)(slots / kWavesPerBlock);
+  HIP_TRY(launch(K.zero, 1, 256, 0, stream, dp));
+  HIP_TRY(launch(K.plan, pblocks, 256, 0, stream, dp));
+  HIP_TRY(launch(K.scan, 1, 64, 0, stream, dp));
+  HIP_TRY(launch(K.scatter, pblocks, 256, 0, stream, dp));
+
+  const bool forced = flags & MICA_FORCE_INT32;
+  const bool any_local = b->mode ? true : b->default_mode == 1;
+  const bool any_sg = b->mode ? true : b->default_mode == 0;
+  const bool may_sat = !forced && !int16_always_safe(max_m, max_n, *s, any_local, any_sg);
+  const bool plain = flags & MICA_PLAIN_LAUNCH;
+  if (!plain && !forced) HIP_TRY(launch(K.persistent[d], fblocks, 256, shmem, stream, dp));
+  // plain launches: every bucket in plain mode, else the buckets the
+  // persistent kernel does not serve
+  bool cls_used[kNumClasses] = {};
+  for (int m = 1; m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
+  for (int kind = 0; kind < kNumKinds; ++kind) {
+    if (forced != (kind == kK32)) continue;
+    if (kind == kK16Sat && !may_sat) continue;
+    for (int cls = 0; cls < kNumClasses; ++cls) {
+      if (!cls_used[cls]) continue;
+      for (int md = 0; md < 2; ++md) {
+        if ((md == 1 && !any_local) || (md == 0 && !any_sg)) continue;
+        const int bk = bucket_id(kind, cls, md);
+        if (!plain && persistent_bucket(bk)) continue;
+        HIP_TRY(launch(K.bucket[d][bk], fblocks, 256, shmem, stream, dp));
+      }
+    }
+  }
+  if (may_sat) HIP_TRY(launch(K.rerun[d], fblocks, 256, shmem, stream, dp));
+  c->last_pairs = b->n_pairs;
+  c->last_slots = (int)slots;
+  c->last_scratch = (size_t)slots * slot_bytes;
+  return MICA_OK;
+}
+
+mica_status_t mica_ctx_last_stats(mica_ctx_t c, void* stream, mica_batch_stats_t* out) {
+  if (!c || !out) return fail(MICA_ERR_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  uint32_t ctr[kNumCounters];
+  HIP_TRY(hipMemcpy(ctr, small_counters(c), sizeof(ctr), hipMemcpyDeviceToHost));
+  out->n_pairs = c->last_pairs;
+  out->n_items = ctr[kCtrItems];
+  out->n_saturated = ctr[kCtrRerun];
+  out->n_waves = c->last_slots;
+  out->scratch_bytes = (int64_t)c->last_scratch;
+  return MICA_OK;
+}
+
+}  // extern "C"
