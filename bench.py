@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the DP phase on one MI355X: GCUPS and % of the integer roofline.
+
+Default workload (one "step" = one call of mica_dp_align_batch over the whole
+batch, inputs already resident in HBM): 1,000,000 reads of 150 bp against
+400 bp windows of a seeded random 100 Mbp reference, semi-global affine DP,
+packed int16 scores with int32 re-run of saturated pairs, outputs score,
+start/end coordinates and CIGAR.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--config c1|c0|c2|c3] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCUPS (150bp semi-global affine DP) + % int roofline; p50/p99 served latency"
+
+# Integer VALU peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz = 3.93e13 32-bit
+# ops/s; packed 16-bit ops (v_pk_*) do two per lane: 7.86e13 ops/s.
+PEAK_I16_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic integer ops per cell (binary ops, a 3-way max counts 2):
+# semi-global score+end 9, +4 direction compares = 13; local score+best 11, +5 = 16.
+OPS_PER_CELL = {("sg", True): 13, ("sg", False): 9, ("local", True): 16, ("local", False): 11}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_batch(cfg, pairs):
+    import synth
+    if cfg == "c0":
+        return synth.config0(**({"n_pairs": pairs} if pairs else {}))
+    if cfg == "c1":
+        return synth.config1(**({"n_pairs": pairs} if pairs else {}))
+    if cfg == "c2":
+        return synth.config2(**({"n_pairs": pairs} if pairs else {}))
+    if cfg == "c3":
+        return synth.config3(**({"n_pairs": pairs} if pairs else {}))
+    raise SystemExit("unknown config " + cfg)
+
+
+WORKLOADS = {
+    "c0": ("1,000 reads of 150 bp vs their own 200 bp windows, semi-global, int32, score + end", "sg", False, True),
+    "c1": ("1,000,000 reads of 150 bp vs 400 bp windows of a 100 Mbp reference, semi-global, "
+           "int16 + int32 re-run, score + start/end + CIGAR", "sg", True, False),
+    "c2": ("500,000 mate-rescue reads of 150 bp vs 1,000 bp windows, local, int16 + int32 re-run, "
+           "score + start/end + CIGAR", "local", True, False),
+    "c3": ("2,000,000 pairs, reads U{50..250} bp vs 1.5m+64 bp windows, half local, one persistent "
+           "launch, score + start/end + CIGAR", "mixed", True, False),
+}
+
+
+def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
+    """Time the CPU oracle on a bounded sample of the same pairs (all host cores up to 16)."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    sc = (1, -4, 6, 1)
+    oracle.align_batch(batch.ref, batch.win_off[:64], batch.win_len[:64], batch.reads, batch.read_off[:64],
+                       batch.read_len[:64], batch.mode[:64], sc, trace=want_trace, threads=threads)
+    n = min(batch.n_pairs, 20000)
+    idx = np.arange(n)
+    t0 = time.time()
+    o = oracle.align_batch(batch.ref, batch.win_off[idx], batch.win_len[idx], batch.reads, batch.read_off[idx],
+                           batch.read_len[idx], batch.mode[idx], sc, trace=want_trace, threads=threads)
+    dt = time.time() - t0
+    if dt < target_s / 3 and n < batch.n_pairs:
+        n = int(min(batch.n_pairs, n * target_s / max(dt, 1e-3)))
+        idx = np.arange(n)
+        t0 = time.time()
+        o = oracle.align_batch(batch.ref, batch.win_off[idx], batch.win_len[idx], batch.reads,
+                               batch.read_off[idx], batch.read_len[idx], batch.mode[idx], sc,
+                               trace=want_trace, threads=threads)
+        dt = time.time() - t0
+    cells = float(np.dot(batch.read_len[idx].astype(np.int64), batch.win_len[idx].astype(np.int64)))
+    # parity of the GPU result on the same sample
+    keys = ["score", "read_end", "ref_end"] + (["read_start", "ref_start", "n_cigar"] if want_trace else [])
+    mism = {k: int((gpu_out[k][idx] != o[k]).sum()) for k in keys}
+    st = (gpu_out["status"][idx].astype(np.uint32) & ~np.uint32(1)) != o["status"]
+    mism["status"] = int(st.sum())
+    if want_trace:
+        cap = o["cigar"].shape[1]
+        ncig = np.minimum(np.abs(o["n_cigar"]), cap)
+        col = np.arange(cap)[None, :] < ncig[:, None]
+        mism["cigar"] = int((((gpu_out["cigar"][idx].astype(np.uint32) != o["cigar"]) & col).any(axis=1)).sum())
+    base = {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": "first %d pairs of the same batch (%.3g cells), %s, %.1f s" % (
+                n, cells, "with traceback" if want_trace else "score + end", dt)}
+    parity = {"pairs": n, "mismatches": mism, "exact": all(v == 0 for v in mism.values())}
+    return base, parity
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--pairs", type=int, default=0, help="override the pair count (testing only)")
+    ap.add_argument("--plain", action="store_true", help="per-bucket launches instead of the persistent one")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(pairs are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1402_4876_amd as mica
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    desc, mode_kind, want_trace, force_i32 = WORKLOADS[args.config]
+    t0 = time.time()
+    batch = make_batch(args.config, args.pairs)
+    log("generated %s: %d pairs, %.3g cells in %.1fs" % (args.config, batch.n_pairs, batch.cells(), time.time() - t0))
+    dev = mica.to_device(batch)
+    n = batch.n_pairs
+    cells = float(batch.cells())
+    max_m = int(batch.read_len.max())
+    max_n = int(batch.win_len.max())
+    cap = 64
+    out = {k: torch.empty(n, dtype=torch.int32, device="cuda") for k in
+           ("score", "read_end", "ref_end", "status", "read_start", "ref_start", "n_cigar")}
+    out["cigar"] = torch.empty((n, cap), dtype=torch.int32, device="cuda")
+    ctx = mica.Context()
+
+    def step():
+        mica.align(ctx, dev["ref2b"], dev["win_off"], dev["win_len"], dev["reads2b"], dev["read_off"],
+                   dev["read_len"], mode=dev["mode"], out_cigar=want_trace, cigar_cap=cap,
+                   force_int32=force_i32, plain=args.plain, max_read_len=max_m, max_win_len=max_n,
+                   ref_len=dev["ref_len"], reads_len=dev["reads_len"], out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.read_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fill_ms, nb = ctx.read_timing()
+    ctx.set_timing(False)
+    stats = ctx.last_stats()
+    ms = (t1 - t0) * 1e3 / args.steps
+    gcups = cells / (ms * 1e-3) / 1e9
+    fill_avg_ms = fill_ms / max(nb, 1)
+    if mode_kind == "mixed":
+        loc = batch.mode == 1
+        ops = float(np.dot(batch.read_len.astype(np.int64), batch.win_len.astype(np.int64) *
+                           np.where(loc, OPS_PER_CELL[("local", want_trace)], OPS_PER_CELL[("sg", want_trace)])))
+    else:
+        ops = cells * OPS_PER_CELL[(mode_kind, want_trace)]
+    peak = PEAK_I32_TOPS if force_i32 else PEAK_I16_TOPS
+    achieved = ops / (fill_avg_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "k_fill_persistent (fill launches of one step)", "kernel_ms": round(fill_avg_ms, 4),
+            "ops_per_cell": round(ops / cells, 3)}
+    host = {k: v.cpu().numpy() for k, v in out.items()}
+    res = {
+        "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32" if force_i32 else "i16", "data": "synthetic",
+        "config": {"workload": desc, "name": args.config, "pairs": n, "cells": cells,
+                   "launch": "plain per-bucket" if args.plain else "persistent"},
+        "roofline": roof,
+        "saturated_pairs": int(stats["n_saturated"]),
+        "resident_waves": int(stats["n_waves"]),
+    }
+    if not args.no_cpu_baseline:
+        base, parity = cpu_baseline(batch, host, want_trace)
+        res["cpu_baseline"] = base
+        res["parity_sample"] = parity
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -80,7 +80,7 @@ enum {
 enum {
   MICA_ST_SATURATED = 1u << 0,   /* 16-bit scores saturated; the 32-bit re-run result is final */
   MICA_ST_CIGAR_TRUNC = 1u << 1, /* n_cigar = -(runs needed); cigar holds the first cigar_cap runs */
-  MICA_ST_LEN_LIMIT = 1u << 2,   /* m or n outside [0, limit]: not computed, outputs zero */
+  MICA_ST_LEN_LIMIT = 1u << 2,   /* m or n outside [0, max_*_len], or mode not 0/1: not computed */
   MICA_ST_WIN_OOB = 1u << 3,     /* window not inside the reference: not computed */
   MICA_ST_READ_OOB = 1u << 4     /* read not inside the read buffer: not computed */
 };
@@ -119,9 +119,10 @@ typedef struct {
   const uint8_t *mode; /* per pair MICA_MODE_*; NULL: every pair uses default_mode */
   int32_t default_mode;
   int64_t n_pairs;
-  /* host-side upper bounds of read_len and win_len over the batch; they size
-   * the scratch and choose the kernels.  A pair above them is computed
-   * correctly only if within the hard limits; it is never unsafe. */
+  /* host-side upper bounds of read_len and win_len over the batch
+   * (<= MICA_MAX_READ_LEN / MICA_MAX_WIN_LEN); they size the scratch and
+   * choose the kernels.  A pair above them is not computed and gets
+   * MICA_ST_LEN_LIMIT. */
   int32_t max_read_len, max_win_len;
   /* outputs (n_pairs entries each) */
   int32_t *score, *read_end, *ref_end; /* always written */
@@ -161,6 +162,14 @@ typedef struct {
   int64_t scratch_bytes;
 } mica_batch_stats_t;
 mica_status_t mica_ctx_last_stats(mica_ctx_t ctx, void *stream, mica_batch_stats_t *out);
+
+/* Kernel timing: with `enable` non-zero, every later mica_dp_align_batch
+ * records a pair of HIP events on its stream around its fill launches (the
+ * DP kernels proper, after planning).  mica_ctx_read_timing waits for the
+ * recorded events, returns the summed fill time in milliseconds and the
+ * number of timed batches since the previous read, and forgets them. */
+mica_status_t mica_ctx_set_timing(mica_ctx_t ctx, int enable);
+mica_status_t mica_ctx_read_timing(mica_ctx_t ctx, double *fill_ms, int64_t *n_batches);
 
 /* Text of the last non-OK status returned on this host thread. */
 const char *mica_last_error(void);

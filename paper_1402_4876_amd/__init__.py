@@ -70,6 +70,17 @@ class Context:
         _lib.check(_lib.load().mica_ctx_last_stats(self._h, _stream_handle(stream), ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in st._fields_}
 
+    def set_timing(self, enable=True):
+        """Record HIP events around the fill launches of every later batch."""
+        _lib.check(_lib.load().mica_ctx_set_timing(self._h, 1 if enable else 0))
+
+    def read_timing(self):
+        """(summed fill milliseconds, number of timed batches) since the last read."""
+        ms = ctypes.c_double()
+        nb = ctypes.c_int64()
+        _lib.check(_lib.load().mica_ctx_read_timing(self._h, ctypes.byref(ms), ctypes.byref(nb)))
+        return ms.value, nb.value
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.load().mica_ctx_destroy(self._h)

@@ -32,7 +32,8 @@ MAX_READ_LEN = 1024
 MAX_WIN_LEN = 8192
 
 EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_pack_2bit",
-           "mica_ctx_set_plan", "mica_ctx_last_stats", "mica_last_error")
+           "mica_ctx_set_plan", "mica_ctx_last_stats", "mica_ctx_set_timing", "mica_ctx_read_timing",
+           "mica_last_error")
 
 
 class Scoring(ctypes.Structure):
@@ -87,6 +88,10 @@ def load():
     lib.mica_ctx_set_plan.restype = ctypes.c_int
     lib.mica_ctx_last_stats.argtypes = [P, P, ctypes.POINTER(BatchStats)]
     lib.mica_ctx_last_stats.restype = ctypes.c_int
+    lib.mica_ctx_set_timing.argtypes = [P, ctypes.c_int]
+    lib.mica_ctx_set_timing.restype = ctypes.c_int
+    lib.mica_ctx_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.mica_ctx_read_timing.restype = ctypes.c_int
     lib.mica_last_error.argtypes = []
     lib.mica_last_error.restype = ctypes.c_char_p
     _lib = lib

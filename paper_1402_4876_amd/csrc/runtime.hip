@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "dp_common.h"
 #include "mica_dp.h"
@@ -57,6 +59,10 @@ struct mica_ctx {
   uint32_t qorder[kNumBuckets];
   uint32_t n_persist_q = 0;
   bool class_dirty = true;
+  // fill-kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   // last batch
   int64_t last_pairs = 0;
   int last_slots = 0;
@@ -125,6 +131,15 @@ mica_status_t ensure_scratch(mica_ctx* c, size_t bytes) {
   return MICA_OK;
 }
 
+hipError_t take_event(mica_ctx* c, hipEvent_t* e) {
+  if (!c->ev_pool.empty()) {
+    *e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
 hipError_t launch(KernelFn fn, unsigned blocks, unsigned threads, size_t shmem, hipStream_t s,
                   const Params* dp) {
   void* args[] = {(void*)&dp};
@@ -191,6 +206,11 @@ mica_status_t mica_ctx_destroy(mica_ctx_t c) {
   if (c->d_class) (void)hipFree(c->d_class);
   if (c->d_pairs) (void)hipFree(c->d_pairs);
   if (c->d_scratch) (void)hipFree(c->d_scratch);
+  for (auto& pr : c->ev_pending) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return MICA_OK;
 }
@@ -333,6 +353,12 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   const bool any_sg = b->mode ? true : b->default_mode == 0;
   const bool may_sat = !forced && !int16_always_safe(max_m, max_n, *s, any_local, any_sg);
   const bool plain = flags & MICA_PLAIN_LAUNCH;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (c->timing) {
+    HIP_TRY(take_event(c, &t0));
+    HIP_TRY(take_event(c, &t1));
+    HIP_TRY(hipEventRecord(t0, stream));
+  }
   if (!plain && !forced) HIP_TRY(launch(K.persistent[d], fblocks, 256, shmem, stream, dp));
   // plain launches: every bucket in plain mode, else the buckets the
   // persistent kernel does not serve
@@ -352,9 +378,37 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     }
   }
   if (may_sat) HIP_TRY(launch(K.rerun[d], fblocks, 256, shmem, stream, dp));
+  if (c->timing) {
+    HIP_TRY(hipEventRecord(t1, stream));
+    c->ev_pending.emplace_back(t0, t1);
+  }
   c->last_pairs = b->n_pairs;
   c->last_slots = (int)slots;
   c->last_scratch = (size_t)slots * slot_bytes;
+  return MICA_OK;
+}
+
+mica_status_t mica_ctx_set_timing(mica_ctx_t c, int enable) {
+  if (!c) return fail(MICA_ERR_INVALID_ARG, "ctx is NULL");
+  c->timing = enable != 0;
+  return MICA_OK;
+}
+
+mica_status_t mica_ctx_read_timing(mica_ctx_t c, double* fill_ms, int64_t* n_batches) {
+  if (!c || !fill_ms || !n_batches) return fail(MICA_ERR_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipSetDevice(c->device));
+  double total = 0;
+  for (auto& pr : c->ev_pending) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    total += ms;
+    c->ev_pool.push_back(pr.first);
+    c->ev_pool.push_back(pr.second);
+  }
+  *fill_ms = total;
+  *n_batches = (int64_t)c->ev_pending.size();
+  c->ev_pending.clear();
   return MICA_OK;
 }
 

@@ -362,3 +362,16 @@ def tiny_random(n_pairs, m_max, n_max, seed, mode=None, related=0.5):
     else:
         md = np.full(n_pairs, mode, np.uint8)
     return _finish("tiny", ref, win_off, n, codes, m, md)
+
+
+def serving_like(n_pairs, ref_len=4_000_000, seed=0):
+    """Config-4-shaped pairs ({100, 150, 250} bp reads, windows 1.5 m + 64) on a
+    small unpacked reference, for parity tests of the serving read mix."""
+    rng = rng_for(5, seed)
+    ref = random_ref(rng, ref_len)
+    mm = rng.choice(np.array(SERVE_LENGTHS, np.int32), n_pairs)
+    nn = (3 * mm) // 2 + 64
+    win_off = (rng.random(n_pairs) * (ref_len - nn + 1)).astype(np.int64)
+    codes, s, e, _ = _draw_reads(rng, lambda pos: ref[pos], win_off, win_off + nn - mm - 8, mm,
+                                 lambda idx: win_off[idx] + nn[idx], 0.01, 0.003, "geom", False)
+    return _finish("c4like", ref, win_off, nn, codes, mm, np.zeros(n_pairs), s - win_off, e - win_off)

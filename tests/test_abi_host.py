@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI library (no GPU compute calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mica_dp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mica_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1402_4876_amd import _lib
+    lib = _lib.load()
+    names = declared_functions()
+    assert "mica_dp_align_batch" in names and len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """ctypes mirrors of the C structs: same size and field offsets as gcc gives."""
+    import subprocess
+    from paper_1402_4876_amd import _lib
+    structs = {"mica_batch_t": _lib.Batch, "mica_scoring_t": _lib.Scoring, "mica_batch_stats_t": _lib.BatchStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mica_dp.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_invalid_arguments_fail_before_any_device_call():
+    from paper_1402_4876_amd import _lib
+    lib = _lib.load()
+    b = _lib.Batch()
+    s = _lib.Scoring(1, -4, 6, 1)
+    assert lib.mica_dp_align_batch(None, ctypes.byref(b), ctypes.byref(s), 0, None) == -1
+    assert b"NULL" in lib.mica_last_error()
+    assert lib.mica_pack_2bit(None, -1, None, None) == -1
+    assert lib.mica_pack_2bit(None, 10, None, None) == -1
+    assert lib.mica_ctx_set_plan(None, 1, 10, 16, 1) == -1
+    assert lib.mica_ctx_destroy(None) == 0
+    h = ctypes.c_void_p()
+    rc = lib.mica_ctx_create(-1, 0, ctypes.byref(h))
+    assert rc in (-1, -4) and not h.value
+
+
+def test_pack_layout():
+    from paper_1402_4876_amd.pack import pack_codes, unpack_words
+    codes = np.random.default_rng(0).integers(0, 4, 1000, dtype=np.uint8)
+    w = pack_codes(codes)
+    assert w.dtype == np.uint32 and len(w) == 63
+    # base k sits at bits 2*(k % 16) of word k // 16
+    for k in (0, 1, 15, 16, 17, 999):
+        assert (int(w[k // 16]) >> (2 * (k % 16))) & 3 == codes[k]
+    assert (int(w[-1]) >> (2 * (1000 % 16))) == 0  # unused high bits are zero
+    assert np.array_equal(unpack_words(w, 1000), codes)
+
+
+def test_binding_refuses_missing_library(tmp_path, monkeypatch):
+    from paper_1402_4876_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib.load()
