@@ -82,7 +82,8 @@ enum {
   MICA_ST_CIGAR_TRUNC = 1u << 1, /* n_cigar = -(runs needed); cigar holds the first cigar_cap runs */
   MICA_ST_LEN_LIMIT = 1u << 2,   /* m or n outside [0, max_*_len], or mode not 0/1: not computed */
   MICA_ST_WIN_OOB = 1u << 3,     /* window not inside the reference: not computed */
-  MICA_ST_READ_OOB = 1u << 4     /* read not inside the read buffer: not computed */
+  MICA_ST_READ_OOB = 1u << 4,    /* read not inside the read buffer: not computed */
+  MICA_ST_INTERNAL = 1u << 5     /* a device consistency check failed; coordinates and CIGAR invalid */
 };
 
 #define MICA_MAX_READ_LEN 1024

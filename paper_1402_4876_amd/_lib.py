@@ -27,6 +27,7 @@ ST_CIGAR_TRUNC = 1 << 1
 ST_LEN_LIMIT = 1 << 2
 ST_WIN_OOB = 1 << 3
 ST_READ_OOB = 1 << 4
+ST_INTERNAL = 1 << 5
 
 MAX_READ_LEN = 1024
 MAX_WIN_LEN = 8192

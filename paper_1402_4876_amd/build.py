@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(HERE, "libmica_dp.so")
+LIB = os.environ.get("MICA_LIB_OUT", os.path.join(HERE, "libmica_dp.so"))
+BUILD = os.environ.get("MICA_BUILD_DIR", BUILD)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MICA_ARCH", "gfx950")
@@ -25,7 +26,7 @@ FLAGS = [
     # no packed fp32 instructions (this code has no fp32 math anyway)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + INCLUDE, "-I" + CSRC,
-]
+] + os.environ.get("MICA_EXTRA_FLAGS", "").split()
 SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
@@ -60,3 +61,23 @@ def build(verbose: bool = True) -> str:
 
 if __name__ == "__main__":
     build()
+
+
+def resource_report(sources=None):
+    """Per-kernel VGPRs, spills and occupancy from the compiler (gfx950).
+
+    Returns a list of (kernel, vgprs, vgpr_spills, scratch_bytes_per_lane,
+    waves_per_simd); the fill kernels are meant to report zero spills.
+    """
+    import re
+    rows = []
+    for src in sources or [f for f in SOURCES if f.startswith(("fill_", "persistent_"))]:
+        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", os.devnull,
+                                 "-Rpass-analysis=kernel-resource-usage"]
+        out = subprocess.run(cmd, capture_output=True, text=True).stderr
+        for blk in out.split("Function Name: ")[1:]:
+            name = blk.split()[0]
+            get = lambda k: int((re.search(k + r": (\d+)", blk) or [0, -1])[1])  # noqa: E731
+            rows.append((name, get("VGPRs"), get("VGPRs Spill"), get(r"ScratchSize \[bytes/lane\]"),
+                         get(r"Occupancy \[waves/SIMD\]")))
+    return rows

@@ -36,14 +36,21 @@ __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
 // The persistent kernel serves the packed 16-bit buckets of the 16-lane
 // classes (the bulk of short-read work); the other buckets run as plain
 // per-bucket launches after it.
+// Classes above kPersistMaxClass (reads over 224 bases) need more registers
+// than the persistent kernels' budget and run as plain launches instead.
+constexpr int kPersistMaxClass = 13;
 __host__ __device__ constexpr bool persistent_bucket(int b) {
-  return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16;
+  return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16 && bucket_class(b) <= kPersistMaxClass;
 }
+// the ordering key of buckets in the work queue: persistent semi-global, then
+// persistent local, then the rest
+__host__ __device__ constexpr int queue_part(int b) { return persistent_bucket(b) ? bucket_mode(b) : 2; }
 
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
 // counters[] slots
-enum : int { kCtrQueueHead = 0, kCtrRerun = 1, kCtrItems = 2, kCtrRerunHead = 3, kNumCounters = 8 };
+// (queue heads of the two persistent kernels: kCtrQueueHead + mode)
+enum : int { kCtrQueueHead = 0, kCtrRerun = 2, kCtrItems = 3, kCtrRerunHead = 4, kNumCounters = 8 };
 
 // per-pair status bits (same values as the public header)
 constexpr uint32_t kStSaturated = 1u << 0;
@@ -51,6 +58,7 @@ constexpr uint32_t kStCigarTrunc = 1u << 1;
 constexpr uint32_t kStLenLimit = 1u << 2;
 constexpr uint32_t kStWinOob = 1u << 3;
 constexpr uint32_t kStReadOob = 1u << 4;
+constexpr uint32_t kStInternal = 1u << 5;
 
 constexpr uint32_t kOutStart = 1u << 0;
 constexpr uint32_t kOutCigar = 1u << 1;
@@ -105,7 +113,7 @@ struct Params {
   uint64_t dir_bytes;          // direction-bit part of a slot
   int32_t stage_stride;        // CIGAR staging words per pair
   int32_t n_slots;             // resident waves the scratch is sized for
-  uint32_t n_persist_q;        // queue positions served by the persistent kernel
+  uint32_t persist_q[3];       // queue positions [persist_q[m], persist_q[m+1]) of mode m's persistent kernel
 };
 
 }  // namespace mica
@@ -115,7 +123,7 @@ typedef void (*KernelFn)(const Params*);
 // Kernel entry points of the library, indexed for the host runtime.
 struct KernelTable {
   KernelFn bucket[2][kNumBuckets];  // [with traceback][bucket]
-  KernelFn persistent[2];
+  KernelFn persistent[2][2];  // [with traceback][mode]
   KernelFn rerun[2];
   KernelFn zero, plan, scan, scatter;
   KernelTable();

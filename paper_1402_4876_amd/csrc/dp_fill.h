@@ -39,6 +39,7 @@ namespace mica {
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ s16x2 as_s(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
 __device__ __forceinline__ uint32_t as_u(s16x2 x) { return __builtin_bit_cast(uint32_t, x); }
@@ -115,11 +116,78 @@ __device__ __forceinline__ uint32_t shift_down(uint32_t src, uint32_t old) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ int base_at(const uint32_t* __restrict__ seq, uint64_t pos) {
+// Data pointers reach the kernels through the parameter block, so the
+// compiler sees them as generic; casting them to the global address space
+// gives global_load/store (flat instructions would also count against the
+// LDS wait counter and stall every step).
+#define MICA_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MICA_GLOBAL T* G(T* p) {
+  return (MICA_GLOBAL T*)p;
+}
+
+// Values the compiler cannot prove wave-uniform (anything derived from the
+// wave index threadIdx.x >> 6) are made uniform explicitly, so they live in
+// SGPRs and the step loops are scalar loops.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+template <class T>
+__device__ __forceinline__ T* uni(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int base_at(const MICA_GLOBAL uint32_t* __restrict__ seq, uint64_t pos) {
   return (int)((seq[pos >> 4] >> (2 * (uint32_t)(pos & 15))) & 3u);
 }
 
-__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+// Minimum resident waves per SIMD the fill kernels are compiled for (bounds
+// their VGPR budget: 512 / waves).
+// Resident waves per SIMD each fill kernel is compiled for (its VGPR budget
+// is 512 / waves), chosen per variant from its register need so that no
+// variant spills: 5 waves <= 102 VGPRs, 4 <= 128, 3 <= 170, 2 <= 256.
+__host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool dir) {
+  const int r = class_rows(cls);
+  if (class_lanes(cls) == 64) return 2;
+  if (kind == kK32) {
+    if (mode == 0) return r <= 9 ? 5 : (r <= 14 ? 4 : 3);
+    return dir ? (r <= 5 ? 5 : (r <= 8 ? 4 : (r <= 12 ? 3 : 2))) : (r <= 6 ? 5 : (r <= 10 ? 4 : 3));
+  }
+  const int sat = kind == kK16Sat ? 1 : 0;
+  if (mode == 0) {
+    if (dir) return r <= 5 - sat ? 5 : (r <= 9 - sat ? 4 : (r <= 14 - sat ? 3 : 2));
+    return r <= 6 - sat ? 5 : (r <= 12 - sat ? 4 : (r <= 16 - sat ? 3 : 2));
+  }
+  if (dir) return r <= 4 - sat ? 4 : (r <= 8 - sat ? 3 : (r <= 15 ? 2 : 1));
+  return r <= 4 - sat ? 5 : (r <= 8 - sat ? 4 : (r <= 13 - sat ? 3 : 2));
+}
+#ifdef MICA_FILL_WAVES
+#define MICA_BUCKET_WAVES(kind, cls, mode, dir) MICA_FILL_WAVES
+#else
+#define MICA_BUCKET_WAVES(kind, cls, mode, dir) fill_waves(kind, cls, mode, dir)
+#endif
+#ifndef MICA_ROW_SCHED_BARRIER
+#define MICA_ROW_SCHED_BARRIER 1
+#endif
+// the persistent kernels hold every 16-lane class of one mode
+#ifndef MICA_PERSIST_WAVES_SG
+#define MICA_PERSIST_WAVES_SG 3
+#endif
+#ifndef MICA_PERSIST_WAVES_LOCAL
+#define MICA_PERSIST_WAVES_LOCAL 2
+#endif
+
+// Lanes of one wave exchange values through LDS: LDS operations of a wave
+// complete in order, and the wave-scope fences keep the compiler from moving
+// a lane's LDS accesses across the exchange point.
+__device__ __forceinline__ void lds_wait() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // One wave-sized work item: G = 64/P groups, each aligning kPairs pairs.
 template <class V, int P, int R, int MODE, bool DIR, bool SAT>
@@ -135,8 +203,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   const int k = lane % P;
   const int sa = prm->sa, sb = prm->sb, so = prm->so, se = prm->se;
   const int oe = so + se;
-  const uint32_t* __restrict__ ref2b = prm->ref2b;
-  const uint32_t* __restrict__ reads2b = prm->reads2b;
+  const MICA_GLOBAL uint32_t* __restrict__ ref2b = G(prm->ref2b);
+  const MICA_GLOBAL uint32_t* __restrict__ reads2b = G(prm->reads2b);
+  const MICA_GLOBAL uint32_t* __restrict__ gpairs = G(uni(pairs));
+  npairs = uni(npairs);
 
   // ---- the pairs of this lane's group --------------------------------------
   int pid[NP], m[NP], n[NP], d0[NP];
@@ -150,22 +220,24 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     woff[h] = 0;
     roff[h] = 0;
     if (idx < npairs) {
-      const int p = (int)pairs[idx];
+      const int p = (int)gpairs[idx];
       pid[h] = p;
-      m[h] = prm->read_len[p];
-      n[h] = prm->win_len[p];
-      woff[h] = prm->win_off[p];
-      roff[h] = prm->read_off[p];
+      m[h] = G(prm->read_len)[p];
+      n[h] = G(prm->win_len)[p];
+      woff[h] = G(prm->win_off)[p];
+      roff[h] = G(prm->read_off)[p];
     }
     d0[h] = PR - m[h];
   }
   // column range of the item (uniform loop, scalar loads)
   int nmin = 1 << 30, nmax = 0;
   for (int s = 0; s < npairs; ++s) {
-    const int nn = prm->win_len[pairs[s]];
+    const int nn = G(prm->win_len)[gpairs[s]];
     nmin = nn < nmin ? nn : nmin;
     nmax = nn > nmax ? nn : nmax;
   }
+  nmin = uni(nmin);
+  nmax = uni(nmax);
 
   // ---- read profile: selector code per row register -------------------------
   uint32_t Q[R];
@@ -246,7 +318,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   uint32_t* ring = lds + g * kRing;
   uint32_t* red = lds + kRingWords + 64 * 2 * 3;  // final (score, i*, j*) per pair
   uint32_t* cand = lds + kRingWords;              // per-lane local candidates
-  uint4* dir4 = reinterpret_cast<uint4*>(slot);
+  MICA_GLOBAL u32x4* dir4 = (MICA_GLOBAL u32x4*)slot;
 
   const T ev = V::splat(se);
   const T oev = V::splat(oe);
@@ -271,14 +343,19 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     lds_wait();
   };
 
+  // window selectors are read two steps ahead of their use
+  fill_ring(0);
+  uint32_t rs_a = ring[(0 - k) & (kRing - 1)];
+  uint32_t rs_b = ring[(1 - k) & (kRing - 1)];
+
   auto step = [&](int t, auto checks) {
     constexpr bool CHECK = decltype(checks)::value;
-    if ((t & (kRing / 2 - 1)) == 0) fill_ring(t);
+    const uint32_t rsel = rs_a;
+    rs_a = rs_b;
     T tup = (T)shift_down<P>((uint32_t)t_last, (uint32_t)tbound);
     T iup = (T)shift_down<P>((uint32_t)i_last, (uint32_t)negv);
     T hdiag = hdiag_next;
     hdiag_next = V::add(tup, oev);
-    const uint32_t rsel = ring[(t - k) & (kRing - 1)];
     const int j = t - k + 1;
     T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
     if (!CHECK || j >= 1) {
@@ -328,12 +405,18 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         D[r] = dn;
         tup = tn;
         iup = in;
+#if MICA_ROW_SCHED_BARRIER
+        // rows in order: keeps the live set to one row's temporaries
+        __builtin_amdgcn_sched_barrier(0);
+#endif
       }
       i_last = iup;
     }
     t_last = Tt[R - 1];
+    if (((t + 2) & (kRing / 2 - 1)) == 0) fill_ring(t + 2);
+    rs_b = ring[(t + 2 - k) & (kRing - 1)];
     if constexpr (DIR) {
-      dir4[t * 64 + lane] = make_uint4((uint32_t)acc0, (uint32_t)acc1, (uint32_t)acc2, (uint32_t)acc3);
+      dir4[t * 64 + lane] = (u32x4){(uint32_t)acc0, (uint32_t)acc1, (uint32_t)acc2, (uint32_t)acc3};
     }
     if constexpr (!LOCAL) {
       // row m sits in the last register of the last lane: column t - P + 2
@@ -463,49 +546,44 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   if constexpr (DIR) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
 
   // ---- outputs and traceback: lane k = h of each group handles pair h --------
-  if (k < NP) {
+  if (k < NP && g * NP + k < npairs) {
+    // the pair's parameters are read again here rather than kept in
+    // registers across the fill loop
     const int h = k;
-    int p_, m_, n_, d0_;
-    uint64_t wo_, ro_;
+    const int p_ = (int)gpairs[g * NP + h];
+    const int m_ = G(prm->read_len)[p_];
+    const int n_ = G(prm->win_len)[p_];
+    const uint64_t wo_ = G(prm->win_off)[p_];
+    const uint64_t ro_ = G(prm->read_off)[p_];
+    const int d0_ = PR - m_;
     bool sat_;
-    if constexpr (NP == 2) {
-      p_ = h ? pid[1] : pid[0];
-      m_ = h ? m[1] : m[0];
-      n_ = h ? n[1] : n[0];
-      d0_ = h ? d0[1] : d0[0];
-      wo_ = h ? woff[1] : woff[0];
-      ro_ = h ? roff[1] : roff[0];
-      sat_ = h ? sat_h[1] : sat_h[0];
-    } else {
-      p_ = pid[0];
-      m_ = m[0];
-      n_ = n[0];
-      d0_ = d0[0];
-      wo_ = woff[0];
-      ro_ = roff[0];
-      sat_ = sat_h[0];
-    }
-    (void)n_;
-    if (p_ >= 0) {
+    if constexpr (NP == 2) sat_ = h ? sat_h[1] : sat_h[0];
+    else sat_ = sat_h[0];
+    {
       if (sat_) {
         const uint32_t pos = atomicAdd(&prm->counters[kCtrRerun], 1u);
-        prm->rerun[pos] = (uint32_t)p_;
+        G(prm->rerun)[pos] = (uint32_t)p_;
       } else {
         const int score = (int)red[(g * NP + h) * 4 + 0] + d0_;
         const int ie = (int)red[(g * NP + h) * 4 + 1];
         const int je = (int)red[(g * NP + h) * 4 + 2];
-        prm->score[p_] = score;
-        prm->read_end[p_] = ie;
-        prm->ref_end[p_] = je;
+        G(prm->score)[p_] = score;
+        G(prm->read_end)[p_] = ie;
+        G(prm->ref_end)[p_] = je;
         uint32_t st = 0;
         if constexpr (DIR) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-          uint32_t* stg = reinterpret_cast<uint32_t*>(slot + prm->dir_bytes) +
-                          (size_t)(g * NP + h) * (size_t)prm->stage_stride;
+          MICA_GLOBAL uint32_t* stg = (MICA_GLOBAL uint32_t*)(slot + prm->dir_bytes) +
+                                      (size_t)(g * NP + h) * (size_t)prm->stage_stride;
           int i = ie, j = je;
           int hval = score;  // true H of the current cell (local zero test)
           int state = 0;     // 0: H, 1: D, 2: I
           int nruns = 0, cur_op = -1, cur_len = 0;
+          // The walk only visits cells 1 <= i <= m, 1 <= j <= n, each step
+          // lowers i or j, so it emits at most ie + je ops.  A cell outside the
+          // matrix can only come from inconsistent direction bits: the walk
+          // then stops and the pair is flagged instead of reading out of range.
+          bool bad = ie < 0 || ie > m_ || je < 0 || je > n_;
           auto emit = [&](int op, int len) {
             if (op == cur_op) {
               cur_len += len;
@@ -515,7 +593,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
               cur_len = len;
             }
           };
-          for (;;) {
+          while (!bad) {
             if (state == 0) {
               if (LOCAL && hval == 0) break;
               if (i == 0) break;
@@ -525,11 +603,15 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
                 break;
               }
             }
+            if (i < 1 || j < 1 || i > m_ || j > n_) {
+              bad = true;
+              break;
+            }
             const int u = d0_ + i - 1;
             const int kk = u / R;
             const int rr = u - kk * R;
             const int ts = j + kk - 1;
-            const uint4 w = dir4[ts * 64 + g * P + kk];
+            const u32x4 w = dir4[ts * 64 + g * P + kk];
             const int bit = h * V::kBitsPerHalf + (R - 1 - rr);
             if (state == 0) {
               if (((w.x >> bit) & 1u) == 0) {
@@ -567,24 +649,29 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             }
           }
           if (cur_len > 0) stg[nruns++] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
+          if (bad) {
+            st |= kStInternal;
+            i = j = 0;
+            nruns = 0;
+          }
           if (prm->flags & (kOutStart | kOutCigar)) {
-            prm->read_start[p_] = i;
-            prm->ref_start[p_] = j;
+            G(prm->read_start)[p_] = i;
+            G(prm->ref_start)[p_] = j;
           }
           if (prm->flags & kOutCigar) {
             const int cap = prm->cigar_cap;
-            uint32_t* out = prm->cigar + (size_t)p_ * (size_t)cap;
+            MICA_GLOBAL uint32_t* out = G(prm->cigar) + (size_t)p_ * (size_t)cap;
             const int ncopy = nruns < cap ? nruns : cap;
             for (int x = 0; x < ncopy; ++x) out[x] = stg[nruns - 1 - x];
             if (nruns > cap) {
               st |= kStCigarTrunc;
-              prm->n_cigar[p_] = -nruns;
+              G(prm->n_cigar)[p_] = -nruns;
             } else {
-              prm->n_cigar[p_] = nruns;
+              G(prm->n_cigar)[p_] = nruns;
             }
           }
         }
-        prm->status[p_] = st;
+        G(prm->status)[p_] = st;
       }
     }
   }
@@ -605,69 +692,69 @@ __device__ __forceinline__ void run_one(const Params* prm, const uint32_t* pairs
     process_item<V16, P, R, MODE, DIR, KIND == kK16Sat>(prm, pairs, np, lds, slot);
 }
 
-template <bool DIR, int CLS = 0>
+template <bool DIR, int MODE, int CLS = 0>
 __device__ __forceinline__ void dispatch(int bucket, const Params* prm, const uint32_t* pairs, int np,
                                          uint32_t* lds, uint8_t* slot) {
-  if constexpr (CLS < kNumClasses && class_lanes(CLS) == 16) {
-    if (bucket_class(bucket) == CLS) {
-      if (bucket_mode(bucket)) run_one<DIR, CLS, kK16, 1>(prm, pairs, np, lds, slot);
-      else run_one<DIR, CLS, kK16, 0>(prm, pairs, np, lds, slot);
-    } else {
-      dispatch<DIR, CLS + 1>(bucket, prm, pairs, np, lds, slot);
-    }
+  if constexpr (CLS <= kPersistMaxClass) {
+    if (bucket_class(bucket) == CLS) run_one<DIR, CLS, kK16, MODE>(prm, pairs, np, lds, slot);
+    else dispatch<DIR, MODE, CLS + 1>(bucket, prm, pairs, np, lds, slot);
   }
 }
 
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Persistent launch: every resident wave takes work items from one queue
-// (buckets in descending cost order) until it is empty.
-template <bool DIR>
-__global__ __launch_bounds__(256) void k_fill_persistent(const Params* __restrict__ prm) {
+// Persistent launch (one per mode): every resident wave takes work items from
+// the mode's part of the queue (buckets in descending cost order) until it is
+// empty.
+template <bool DIR, int MODE>
+__global__ __launch_bounds__(256, MODE ? MICA_PERSIST_WAVES_LOCAL : MICA_PERSIST_WAVES_SG) void
+k_fill_persistent(const Params* __restrict__ prm) {
   extern __shared__ uint32_t smem[];
-  const int wave = threadIdx.x >> 6;
+  const int wave = uni((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int slot_id = blockIdx.x * kWavesPerBlock + wave;
   if (slot_id >= prm->n_slots) return;
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
-  const uint32_t total = prm->qstart[prm->n_persist_q];
+  const int q0 = (int)prm->persist_q[MODE], q1 = (int)prm->persist_q[MODE + 1];
+  const uint32_t base_item = G(prm->qstart)[q0];
+  const uint32_t total = G(prm->qstart)[q1];
   for (;;) {
     uint32_t v = 0;
-    if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead], 1u);
-    const uint32_t item = wave_uniform(v);
+    if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead + MODE], 1u);
+    const uint32_t item = base_item + wave_uniform(v);
     if (item >= total) break;
     // queue position: last q with qstart[q] <= item
-    int lo = 0, hi = (int)prm->n_persist_q - 1;
+    int lo = q0, hi = q1 - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (prm->qstart[mid] <= item) lo = mid;
+      if (G(prm->qstart)[mid] <= item) lo = mid;
       else hi = mid - 1;
     }
-    const int bucket = (int)prm->qorder[lo];
-    const uint32_t idx = item - prm->qstart[lo];
+    const int bucket = (int)G(prm->qorder)[lo];
+    const uint32_t idx = item - G(prm->qstart)[lo];
     const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
     const uint32_t first = idx * (uint32_t)ppi;
-    const uint32_t cnt = prm->bcount[bucket];
+    const uint32_t cnt = G(prm->bcount)[bucket];
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    dispatch<DIR>(bucket, prm, prm->sorted + prm->bstart[bucket] + first, np, lds, slot);
+    dispatch<DIR, MODE>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
   }
 }
 
 // Plain launch: one bucket per kernel, waves stride over its items.
 template <bool DIR, int KIND, int CLS, int MODE>
-__global__ __launch_bounds__(256) void k_fill_bucket(const Params* __restrict__ prm) {
+__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, DIR)) void k_fill_bucket(const Params* __restrict__ prm) {
   extern __shared__ uint32_t smem[];
-  const int wave = threadIdx.x >> 6;
+  const int wave = uni((int)(threadIdx.x >> 6));
   const int slot_id = blockIdx.x * kWavesPerBlock + wave;
   if (slot_id >= prm->n_slots) return;
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
   constexpr int bucket = bucket_id(KIND, CLS, MODE);
   constexpr int ppi = pairs_per_item(KIND, CLS);
-  const uint32_t cnt = prm->bcount[bucket];
+  const uint32_t cnt = G(prm->bcount)[bucket];
   const uint32_t items = (cnt + ppi - 1) / ppi;
-  const uint32_t* base = prm->sorted + prm->bstart[bucket];
+  const uint32_t* base = prm->sorted + G(prm->bstart)[bucket];
   for (uint32_t it = (uint32_t)slot_id; it < items; it += (uint32_t)prm->n_slots) {
     const uint32_t first = it * ppi;
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);

@@ -8,7 +8,7 @@ namespace mica {
 template <bool DIR>
 __global__ __launch_bounds__(256) void k_rerun(const Params* __restrict__ prm) {
   extern __shared__ uint32_t smem[];
-  const int wave = threadIdx.x >> 6;
+  const int wave = uni((int)(threadIdx.x >> 6));
   const int slot_id = blockIdx.x * kWavesPerBlock + wave;
   if (slot_id >= prm->n_slots) return;
   uint32_t* lds = smem + wave * kLdsWaveWords;
@@ -114,6 +114,7 @@ __global__ void k_scan(const Params* __restrict__ prm) {
   prm->qstart[kNumBuckets] = items;
   prm->counters[kCtrItems] = items;
   prm->counters[kCtrQueueHead] = 0;
+  prm->counters[kCtrQueueHead + 1] = 0;
   prm->counters[kCtrRerun] = 0;
 }
 
@@ -160,14 +161,18 @@ namespace mica {
   X(k16s, 0, 0) X(k16s, 0, 1) X(k16s, 1, 0) X(k16s, 1, 1) \
   X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1)
 MICA_FILL_ALL(MICA_FILL_DECL)
-void reg_persistent_0(KernelTable& t);
-void reg_persistent_1(KernelTable& t);
+void reg_persistent_0_0(KernelTable& t);
+void reg_persistent_0_1(KernelTable& t);
+void reg_persistent_1_0(KernelTable& t);
+void reg_persistent_1_1(KernelTable& t);
 
 KernelTable::KernelTable() {
 #define MICA_FILL_CALL(kind, mode, dir) reg_fill_##kind##_##mode##_##dir(*this);
   MICA_FILL_ALL(MICA_FILL_CALL)
-  reg_persistent_0(*this);
-  reg_persistent_1(*this);
+  reg_persistent_0_0(*this);
+  reg_persistent_0_1(*this);
+  reg_persistent_1_0(*this);
+  reg_persistent_1_1(*this);
   rerun[0] = &k_rerun<false>;
   rerun[1] = &k_rerun<true>;
   zero = &k_zero;

@@ -57,7 +57,7 @@ struct mica_ctx {
   int ring_pos = 0;
   uint8_t class_of_m[kMaxM + 1];
   uint32_t qorder[kNumBuckets];
-  uint32_t n_persist_q = 0;
+  uint32_t persist_q[3] = {0, 0, 0};
   bool class_dirty = true;
   // fill-kernel timing
   bool timing = false;
@@ -168,8 +168,12 @@ mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t
   const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
   for (int d = 0; d < 2; ++d) {
     int nb = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kernels().persistent[d], 256, shmem));
-    c->occ_blocks[d] = std::max(nb, 1);
+    int best = 1;
+    for (int m = 0; m < 2; ++m) {
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kernels().persistent[d][m], 256, shmem));
+      best = std::max(best, nb);
+    }
+    c->occ_blocks[d] = best;
   }
   HIP_TRY(hipMalloc(&c->d_params, sizeof(Params) * kParamRing));
   HIP_TRY(hipMalloc(&c->d_small, kSmallWords * sizeof(uint32_t)));
@@ -180,12 +184,16 @@ mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t
   // queue order: buckets by descending item cost
   int order[kNumBuckets];
   for (int b = 0; b < kNumBuckets; ++b) order[b] = b;
-  // buckets of the persistent kernel first, each part by descending item cost
+  // buckets of the persistent kernels first (semi-global, then local), each
+  // part by descending item cost
   std::stable_sort(order, order + kNumBuckets, [](int x, int y) {
-    if (persistent_bucket(x) != persistent_bucket(y)) return persistent_bucket(x);
+    if (queue_part(x) != queue_part(y)) return queue_part(x) < queue_part(y);
     return bucket_cost(x) > bucket_cost(y);
   });
-  for (int b = 0; b < kNumBuckets; ++b) c->n_persist_q += persistent_bucket(b) ? 1 : 0;
+  for (int b = 0; b < kNumBuckets; ++b) {
+    if (queue_part(b) == 0) c->persist_q[1]++;
+    if (queue_part(b) <= 1) c->persist_q[2]++;
+  }
   for (int q = 0; q < kNumBuckets; ++q) c->qorder[q] = (uint32_t)order[q];
   HIP_TRY(hipMemcpy(small_qorder(c), c->qorder, sizeof(c->qorder), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_class, c->class_of_m, kMaxM + 1, hipMemcpyHostToDevice));
@@ -333,7 +341,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.dir_bytes = dir_bytes;
   P.stage_stride = stage_stride;
   P.n_slots = (int32_t)slots;
-  P.n_persist_q = c->n_persist_q;
+  for (int i = 0; i < 3; ++i) P.persist_q[i] = c->persist_q[i];
   Params* dp = c->d_params + rp;
   HIP_TRY(hipMemcpyAsync(dp, &P, sizeof(Params), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(c->ev[rp], stream));
@@ -359,7 +367,10 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     HIP_TRY(take_event(c, &t1));
     HIP_TRY(hipEventRecord(t0, stream));
   }
-  if (!plain && !forced) HIP_TRY(launch(K.persistent[d], fblocks, 256, shmem, stream, dp));
+  if (!plain && !forced) {
+    if (any_sg) HIP_TRY(launch(K.persistent[d][0], fblocks, 256, shmem, stream, dp));
+    if (any_local) HIP_TRY(launch(K.persistent[d][1], fblocks, 256, shmem, stream, dp));
+  }
   // plain launches: every bucket in plain mode, else the buckets the
   // persistent kernel does not serve
   bool cls_used[kNumClasses] = {};
