@@ -32,6 +32,26 @@ PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 # semi-global score+end 9, +4 direction compares = 13; local score+best 11, +5 = 16.
 OPS_PER_CELL = {("sg", True): 13, ("sg", False): 9, ("local", True): 16, ("local", False): 11}
 
+# HBM bytes per launch of the dominant fill kernel from two rocprofv3 passes
+# (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a 1 GiB
+# device copy (2048 bytes per FETCH_SIZE unit, 1024 per WRITE_SIZE unit).
+# They hold only for the kernel source they were taken on, identified by the
+# SHA-256 of the fill kernel's sources; for any other source the bench line
+# reports traffic as null.
+KERNEL_SOURCES = ("dp_fill.h", "dp_common.h")
+MEASURED_TRAFFIC = {
+    # config: (kernel source sha256, fetch bytes, write bytes)
+}
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1402_4876_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -100,6 +120,19 @@ def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
     return base, parity
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
+    gives the counter-to-bytes factor used for the DP kernel's HBM traffic."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +142,11 @@ def main():
     ap.add_argument("--pairs", type=int, default=0, help="override the pair count (testing only)")
     ap.add_argument("--plain", action="store_true", help="per-bucket launches instead of the persistent one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(pairs are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
@@ -136,10 +173,14 @@ def main():
            ("score", "read_end", "ref_end", "status", "read_start", "ref_start", "n_cigar")}
     out["cigar"] = torch.empty((n, cap), dtype=torch.int32, device="cuda")
     ctx = mica.Context()
+    # a batch of one mode passes no per-pair mode array
+    uniform = bool((batch.mode == batch.mode[0]).all()) if n else True
+    mode_arg = None if uniform else dev["mode"]
+    default_mode = int(batch.mode[0]) if (uniform and n) else 0
 
     def step():
         mica.align(ctx, dev["ref2b"], dev["win_off"], dev["win_len"], dev["reads2b"], dev["read_off"],
-                   dev["read_len"], mode=dev["mode"], out_cigar=want_trace, cigar_cap=cap,
+                   dev["read_len"], mode=mode_arg, default_mode=default_mode, out_cigar=want_trace, cigar_cap=cap,
                    force_int32=force_i32, plain=args.plain, max_read_len=max_m, max_win_len=max_n,
                    ref_len=dev["ref_len"], reads_len=dev["reads_len"], out=out)
 
@@ -172,6 +213,12 @@ def main():
             "frac": round(achieved / peak, 4), "traffic": None,
             "kernel": "k_fill_persistent (fill launches of one step)", "kernel_ms": round(fill_avg_ms, 4),
             "ops_per_cell": round(ops / cells, 3)}
+    meas = MEASURED_TRAFFIC.get(args.config)
+    if meas and meas[0] == kernel_source_sha():
+        roof["traffic"] = meas[1] + meas[2]
+        roof["traffic_split"] = {"fetch": meas[1], "write": meas[2]}
+    else:
+        roof["traffic_note"] = "no FETCH_SIZE/WRITE_SIZE counters taken for this kernel source"
     host = {k: v.cpu().numpy() for k, v in out.items()}
     res = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
