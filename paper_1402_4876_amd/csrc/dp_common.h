@@ -38,7 +38,10 @@ __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
 // per-bucket launches after it.
 // Classes above kPersistMaxClass (reads over 224 bases) need more registers
 // than the persistent kernels' budget and run as plain launches instead.
-constexpr int kPersistMaxClass = 13;
+#ifndef MICA_PERSIST_MAX_CLASS
+#define MICA_PERSIST_MAX_CLASS 13
+#endif
+constexpr int kPersistMaxClass = MICA_PERSIST_MAX_CLASS;
 __host__ __device__ constexpr bool persistent_bucket(int b) {
   return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16 && bucket_class(b) <= kPersistMaxClass;
 }

@@ -23,10 +23,12 @@
 //    XOR of a per-row read code and a per-column window code, the table holds
 //    the match and mismatch scores; a dummy row's code selects 0xFF bytes (-1).
 //  * Per cell and per direction kind one sign bit is kept (diagonal / deletion
-//    wins, deletion / insertion extends); the bits of a lane's rows for one
-//    step form one 32-bit word per kind, stored to the wave's scratch slot.
-//    After the fill one lane per pair walks them back to the start cell and
-//    writes the CIGAR.
+//    loses, deletion / insertion extends).  One v_perm_b32 turns the signs of
+//    two kinds' differences into 0x00/0xFF bytes and one v_and_or_b32 keeps
+//    the row's bit of each byte: word 2*(r/8) + kind/2, byte 2*(kind%2) + half,
+//    bit r%8.  A lane stores two words per step (four when R > 8) to the
+//    wave's scratch slot; after the fill one lane per pair walks them back to
+//    the start cell and writes the CIGAR.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -40,14 +42,33 @@ namespace mica {
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ s16x2 as_s(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
 __device__ __forceinline__ uint32_t as_u(s16x2 x) { return __builtin_bit_cast(uint32_t, x); }
 __device__ __forceinline__ uint32_t as_u(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
 
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), in order
+template <class F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 __device__ __forceinline__ int clamp16(int v) { return v < -32768 ? -32768 : (v > 32767 ? 32767 : v); }
 __device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t x, uint32_t y) {
   return (mask & x) | (~mask & y);
+}
+
+// One v_bfi_b32 (mask & x | ~mask & y).  Written out because the compiler
+// would otherwise split a chain of them into and/or trees of twice the length.
+__device__ __forceinline__ uint32_t bfi_op(uint32_t mask, uint32_t x, uint32_t y) {
+  uint32_t d;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(d) : "s"(mask), "v"(x), "v"(y));
+  return d;
 }
 
 // Packed 16-bit scores: half h of every register belongs to pair h of the group.
@@ -61,10 +82,9 @@ struct V16 {
   __device__ static T vmax(T a, T b) { return as_u(__builtin_elementwise_max(as_s(a), as_s(b))); }
   __device__ static T vmin(T a, T b) { return as_u(__builtin_elementwise_min(as_s(a), as_s(b))); }
   __device__ static T max3(T a, T b, T c) { return vmax(vmax(a, b), c); }
-  // append the sign bit of each half of d at bits 0 and 16
-  __device__ static T push(T acc, T d) {
-    return (acc << 1) | as_u(__builtin_bit_cast(u16x2, d) >> (u16x2){15, 15});
-  }
+  // v_perm_b32 selector that turns the signs of two difference registers
+  // (a, b) into four 0x00/0xFF bytes: b.lo, b.hi, a.lo, a.hi
+  static constexpr uint32_t kSignSel = 0x0B0A0908u;
   // 0xFFFF in each half where d < 0
   __device__ static T negmask(T d) { return as_u(as_s(d) >> (s16x2){15, 15}); }
   __device__ static T make2(int lo, int hi) {
@@ -79,7 +99,6 @@ struct V16 {
   }
   __device__ static uint32_t qdummy(int h) { return 0xF0F0u << (16 * h); }
   __device__ static uint32_t rcode(int r, int h) { return ((uint32_t)r * 0x0202u) << (16 * h); }
-  static constexpr int kBitsPerHalf = 16;
 };
 
 // 32-bit scores, one pair per group.
@@ -92,9 +111,8 @@ struct V32 {
   __device__ static T vmax(T a, T b) { return a > b ? a : b; }
   __device__ static T vmin(T a, T b) { return a < b ? a : b; }
   __device__ static T max3(T a, T b, T c) { return vmax(vmax(a, b), c); }
-  __device__ static T push(T acc, T d) {
-    return (T)__builtin_amdgcn_alignbit((uint32_t)acc, (uint32_t)d, 31);  // (acc << 1) | (d >> 31)
-  }
+  // sign bytes b, b, a, a (the byte layout of the 16-bit variant, half 1 a copy of half 0)
+  static constexpr uint32_t kSignSel = 0x0B0B0909u;
   __device__ static T splat(int v) { return v; }
   __device__ static int get(T x, int) { return x; }
   // bytes: 2q, 2q+1 pick a 16-bit table entry, 8+q replicate its sign
@@ -104,7 +122,6 @@ struct V32 {
   }
   __device__ static uint32_t qdummy(int) { return 0xF0F0F0F0u; }
   __device__ static uint32_t rcode(int r, int) { return (uint32_t)r * 0x01010202u; }
-  static constexpr int kBitsPerHalf = 32;
 };
 
 template <int P>
@@ -318,7 +335,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   uint32_t* ring = lds + g * kRing;
   uint32_t* red = lds + kRingWords + 64 * 2 * 3;  // final (score, i*, j*) per pair
   uint32_t* cand = lds + kRingWords;              // per-lane local candidates
+  // direction words per lane and step
+  constexpr int NW = R <= 8 ? 2 : 4;
   MICA_GLOBAL u32x4* dir4 = (MICA_GLOBAL u32x4*)slot;
+  MICA_GLOBAL u32x2* dir2 = (MICA_GLOBAL u32x2*)slot;
 
   const T ev = V::splat(se);
   const T oev = V::splat(oe);
@@ -357,7 +377,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     T hdiag = hdiag_next;
     hdiag_next = V::add(tup, oev);
     const int j = t - k + 1;
-    T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    uint32_t acc[4] = {0u, 0u, 0u, 0u};
     if (!CHECK || j >= 1) {
       T jj = (T)0, vmask = (T)0;
       if constexpr (LOCAL) {
@@ -368,8 +388,8 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
           jj = (T)j;
         }
       }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
+      static_for<R>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
         const T s = (T)__builtin_amdgcn_perm(tab_hi, tab_lo, Q[r] ^ rsel);
         const T x = V::add(hdiag, s);
         const T dn = V::vmax(V::sub(D[r], ev), Tt[r]);
@@ -378,10 +398,22 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         if constexpr (LOCAL) h = V::vmax(h, floor_v);
         const T tn = V::sub(h, oev);
         if constexpr (DIR) {
-          acc0 = V::push(acc0, V::sub(x, h));      // 1: diagonal loses
-          acc1 = V::push(acc1, V::sub(dn, h));     // 1: deletion loses
-          acc2 = V::push(acc2, V::sub(Tt[r], dn)); // 1: deletion extends
-          acc3 = V::push(acc3, V::sub(tup, in));   // 1: insertion extends
+          // sign set: kind 0 diagonal loses, 1 deletion loses, 2 deletion
+          // extends, 3 insertion extends
+          // the first row of a word takes the whole sign bytes, each later
+          // row keeps the bits below it and overwrites the rest (bits above
+          // the word's last row are copies of that row and never read)
+          const uint32_t s01 = __builtin_amdgcn_perm((uint32_t)V::sub(dn, h), (uint32_t)V::sub(x, h), V::kSignSel);
+          const uint32_t s23 = __builtin_amdgcn_perm((uint32_t)V::sub(tup, in), (uint32_t)V::sub(Tt[r], dn), V::kSignSel);
+          constexpr int w = (r >> 3) * 2;
+          if constexpr ((r & 7) == 0) {
+            acc[w] = s01;
+            acc[w + 1] = s23;
+          } else {
+            constexpr uint32_t low = ((1u << (r & 7)) - 1u) * 0x01010101u;
+            acc[w] = bfi_op(low, acc[w], s01);
+            acc[w + 1] = bfi_op(low, acc[w + 1], s23);
+          }
         }
         if constexpr (LOCAL) {
           if constexpr (NP == 2) {
@@ -409,14 +441,17 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         // rows in order: keeps the live set to one row's temporaries
         __builtin_amdgcn_sched_barrier(0);
 #endif
-      }
+      });
       i_last = iup;
     }
     t_last = Tt[R - 1];
     if (((t + 2) & (kRing / 2 - 1)) == 0) fill_ring(t + 2);
     rs_b = ring[(t + 2 - k) & (kRing - 1)];
     if constexpr (DIR) {
-      dir4[t * 64 + lane] = (u32x4){(uint32_t)acc0, (uint32_t)acc1, (uint32_t)acc2, (uint32_t)acc3};
+      if constexpr (NW == 4)
+        dir4[t * 64 + lane] = (u32x4){acc[0], acc[1], acc[2], acc[3]};
+      else
+        dir2[t * 64 + lane] = (u32x2){acc[0], acc[1]};
     }
     if constexpr (!LOCAL) {
       // row m sits in the last register of the last lane: column t - P + 2
@@ -446,6 +481,12 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   const int t_end = nmax + P - 1;
   int t = 0;
   for (; t < (P - 1 < t_end ? P - 1 : t_end); ++t) step(t, std::true_type{});
+  // two steps per iteration: each step's new H goes to the registers the
+  // step before freed, so the loop needs no copies at its back edge
+  for (; t + 1 < nmin; t += 2) {
+    step(t, std::false_type{});
+    step(t + 1, std::false_type{});
+  }
   for (; t < nmin; ++t) step(t, std::false_type{});
   for (; t < t_end; ++t) step(t, std::true_type{});
 
@@ -611,10 +652,19 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             const int kk = u / R;
             const int rr = u - kk * R;
             const int ts = j + kk - 1;
-            const u32x4 w = dir4[ts * 64 + g * P + kk];
-            const int bit = h * V::kBitsPerHalf + (R - 1 - rr);
+            uint32_t w01, w23;
+            if constexpr (NW == 4) {
+              const u32x4 w = dir4[ts * 64 + g * P + kk];
+              w01 = rr >= 8 ? w.z : w.x;
+              w23 = rr >= 8 ? w.w : w.y;
+            } else {
+              const u32x2 w = dir2[ts * 64 + g * P + kk];
+              w01 = w.x;
+              w23 = w.y;
+            }
+            const int bit = 8 * h + (rr & 7);  // kinds 0 and 2 at bit, 1 and 3 at bit + 16
             if (state == 0) {
-              if (((w.x >> bit) & 1u) == 0) {
+              if (((w01 >> bit) & 1u) == 0) {
                 emit(0, 1);
                 if (LOCAL) {
                   const int qb = base_at(reads2b, ro_ + (uint64_t)(i - 1));
@@ -623,14 +673,14 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
                 }
                 --i;
                 --j;
-              } else if (((w.y >> bit) & 1u) == 0) {
+              } else if (((w01 >> (bit + 16)) & 1u) == 0) {
                 state = 1;
               } else {
                 state = 2;
               }
             } else if (state == 1) {
               emit(2, 1);
-              if ((w.z >> bit) & 1u) {
+              if ((w23 >> bit) & 1u) {
                 hval += se;
               } else {
                 hval += oe;
@@ -639,7 +689,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
               --j;
             } else {
               emit(1, 1);
-              if ((w.w >> bit) & 1u) {
+              if ((w23 >> (bit + 16)) & 1u) {
                 hval += se;
               } else {
                 hval += oe;
