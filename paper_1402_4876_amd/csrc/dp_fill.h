@@ -169,16 +169,16 @@ __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool d
   const int r = class_rows(cls);
   if (class_lanes(cls) == 64) return 2;
   if (kind == kK32) {
-    if (mode == 0) return r <= 9 ? 5 : (r <= 14 ? 4 : 3);
+    if (mode == 0) return r <= 8 ? 5 : (r <= 11 ? 4 : 3);
     return dir ? (r <= 5 ? 5 : (r <= 8 ? 4 : (r <= 12 ? 3 : 2))) : (r <= 6 ? 5 : (r <= 10 ? 4 : 3));
   }
   const int sat = kind == kK16Sat ? 1 : 0;
   if (mode == 0) {
-    if (dir) return r <= 5 - sat ? 5 : (r <= 9 - sat ? 4 : (r <= 14 - sat ? 3 : 2));
-    return r <= 6 - sat ? 5 : (r <= 12 - sat ? 4 : (r <= 16 - sat ? 3 : 2));
+    if (dir) return r <= 5 - sat ? 5 : (r <= 9 - sat ? 4 : (r <= 14 - 2 * sat ? 3 : 2));
+    return r <= 6 - sat ? 5 : (r <= 12 - 3 * sat ? 4 : (r <= 16 - 2 * sat ? 3 : 2));
   }
   if (dir) return r <= 4 - sat ? 4 : (r <= 8 - sat ? 3 : (r <= 15 ? 2 : 1));
-  return r <= 4 - sat ? 5 : (r <= 8 - sat ? 4 : (r <= 13 - sat ? 3 : 2));
+  return r <= 4 - sat ? 5 : (r <= 8 - sat ? 4 : (r <= 12 - sat ? 3 : 2));
 }
 #ifdef MICA_FILL_WAVES
 #define MICA_BUCKET_WAVES(kind, cls, mode, dir) MICA_FILL_WAVES
@@ -625,6 +625,16 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
           // matrix can only come from inconsistent direction bits: the walk
           // then stops and the pair is flagged instead of reading out of range.
           bool bad = ie < 0 || ie > m_ || je < 0 || je > n_;
+          // The walk reads direction words through a window of WW steps of
+          // one lane in LDS (the ring area, free after the fill): a path
+          // spends about R steps in a lane, so most lanes take one burst.
+          constexpr int WW = NP == 1 ? 4 : (NW == 4 ? (SAT ? 6 : 8) : (R + 3 < 8 ? R + 3 : 8));
+          static_assert(NP * WW * NW <= kRing, "walk windows exceed the group's ring");
+          uint32_t* win = ring + h * (WW * NW);
+          int win_k = -1, win_top = -1;
+          // local mode: the read and window words of the current bases
+          uint64_t q_idx = ~0ull, r_idx = ~0ull;
+          uint32_t q_word = 0, r_word = 0;
           auto emit = [&](int op, int len) {
             if (op == cur_op) {
               cur_len += len;
@@ -652,13 +662,34 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             const int kk = u / R;
             const int rr = u - kk * R;
             const int ts = j + kk - 1;
+            if (kk != win_k || ts > win_top || ts <= win_top - WW) {
+              // steps ts, ts-1, ... of lane kk in one burst of independent
+              // loads (clamped at step kk, the lane's first real column),
+              // then into the walker's LDS window
+              win_k = kk;
+              win_top = ts;
+              const int base = g * P + kk;
+              if constexpr (NW == 4) {
+                u32x4 tmp[WW];
+#pragma unroll
+                for (int x = 0; x < WW; ++x) tmp[x] = dir4[(ts - x >= kk ? ts - x : kk) * 64 + base];
+#pragma unroll
+                for (int x = 0; x < WW; ++x) *(u32x4*)(win + 4 * x) = tmp[x];
+              } else {
+                u32x2 tmp[WW];
+#pragma unroll
+                for (int x = 0; x < WW; ++x) tmp[x] = dir2[(ts - x >= kk ? ts - x : kk) * 64 + base];
+#pragma unroll
+                for (int x = 0; x < WW; ++x) *(u32x2*)(win + 2 * x) = tmp[x];
+              }
+            }
             uint32_t w01, w23;
             if constexpr (NW == 4) {
-              const u32x4 w = dir4[ts * 64 + g * P + kk];
+              const u32x4 w = *(const u32x4*)(win + 4 * (win_top - ts));
               w01 = rr >= 8 ? w.z : w.x;
               w23 = rr >= 8 ? w.w : w.y;
             } else {
-              const u32x2 w = dir2[ts * 64 + g * P + kk];
+              const u32x2 w = *(const u32x2*)(win + 2 * (win_top - ts));
               w01 = w.x;
               w23 = w.y;
             }
@@ -667,8 +698,17 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
               if (((w01 >> bit) & 1u) == 0) {
                 emit(0, 1);
                 if (LOCAL) {
-                  const int qb = base_at(reads2b, ro_ + (uint64_t)(i - 1));
-                  const int rb = base_at(ref2b, wo_ + (uint64_t)(j - 1));
+                  const uint64_t qp = ro_ + (uint64_t)(i - 1), rp = wo_ + (uint64_t)(j - 1);
+                  if ((qp >> 4) != q_idx) {
+                    q_idx = qp >> 4;
+                    q_word = reads2b[q_idx];
+                  }
+                  if ((rp >> 4) != r_idx) {
+                    r_idx = rp >> 4;
+                    r_word = ref2b[r_idx];
+                  }
+                  const uint32_t qb = (q_word >> (2 * (uint32_t)(qp & 15))) & 3u;
+                  const uint32_t rb = (r_word >> (2 * (uint32_t)(rp & 15))) & 3u;
                   hval -= (qb == rb) ? sa : sb;
                 }
                 --i;
