@@ -4,8 +4,9 @@
  *
  * What it computes (MICA paper, Methods, "Highly parallel dynamic
  * programming"): reads that few-mismatch search could not place are aligned
- * by DP "with indels" (architecture section) against a candidate region of
- * the reference, with the affine gap model of three tables M, I and D
+ * by DP allowing insertions and deletions (architecture section) against a
+ * candidate region of the reference, with the affine gap model of three
+ * tables M, I and D
  * holding the best score of an alignment ending in a Match, an Insert or a
  * Delete.  Cell (i,j) of the table depends on (i-1,j-1), (i-1,j) and
  * (i,j-1).  DP is used where indels and soft clipping are needed, hence two
@@ -73,7 +74,8 @@ enum {
   MICA_OUT_START = 1u << 0,   /* write read_start and ref_start (runs the traceback) */
   MICA_OUT_CIGAR = 1u << 1,   /* write cigar and n_cigar (implies MICA_OUT_START) */
   MICA_FORCE_INT32 = 1u << 8, /* compute every pair with 32-bit scores */
-  MICA_PLAIN_LAUNCH = 1u << 9 /* one launch per length bucket instead of the persistent one */
+  MICA_PLAIN_LAUNCH = 1u << 9, /* one launch per length bucket instead of the persistent one */
+  MICA_NO_GRAPH = 1u << 10     /* enqueue the kernels one by one instead of as one HIP graph */
 };
 
 /* per-pair status bits */
@@ -138,7 +140,11 @@ typedef struct {
  * Enqueues all work on `stream` (a hipStream_t; NULL = the null stream) and
  * returns without synchronising.  The result of every pair is exact: pairs
  * computed with 16-bit scores whose values reach the saturation guard band
- * are recomputed with 32-bit scores on the device (MICA_ST_SATURATED). */
+ * are recomputed with 32-bit scores on the device (MICA_ST_SATURATED).
+ * The kernels of one call (planning, fill, re-run) are one HIP graph launch:
+ * the context builds a graph per distinct launch sequence on first use and
+ * then only updates its grid sizes and parameter block (MICA_NO_GRAPH
+ * launches the same kernels one by one). */
 mica_status_t mica_dp_align_batch(mica_ctx_t ctx, const mica_batch_t *batch,
                                   const mica_scoring_t *scoring, uint32_t flags, void *stream);
 
@@ -148,11 +154,48 @@ mica_status_t mica_dp_align_batch(mica_ctx_t ctx, const mica_batch_t *batch,
 mica_status_t mica_pack_2bit(const uint8_t *codes, int64_t n_bases, uint32_t *words, void *stream);
 
 /* Kernel plan for reads of length in [m_lo, m_hi]: `lanes` lanes per pair
- * (16 or 64) and `rows` read rows per lane (1..16), lanes * rows >= m_hi.
- * Lengths not covered keep the default plan.  Plans only change speed, never
- * results. */
+ * and `rows` read rows per lane, lanes * rows >= m_hi; (16, 1..16) or
+ * (64, 4), (64, 8), (64, 16).  The default plan is (16, ceil(m/16)) up to 256
+ * bases and (64, 16) above.  Lengths not covered keep their plan.  Plans
+ * change only speed, never results.  Call between batches: the table is
+ * copied to the device synchronously. */
 mica_status_t mica_ctx_set_plan(mica_ctx_t ctx, int32_t m_lo, int32_t m_hi, int32_t lanes,
                                 int32_t rows);
+
+/* One read-length range of a tuned plan. */
+typedef struct {
+  int32_t m_lo, m_hi;  /* read lengths of the range */
+  int32_t lanes, rows; /* plan chosen for it */
+  int32_t n_pairs;     /* sample pairs in the range that were timed */
+  int32_t n_candidates;
+  int32_t n_rejected;  /* candidates whose outputs differed from the default plan's */
+  int32_t pad_;
+  double ms;           /* time of one call on those pairs with the chosen plan */
+  double default_ms;   /* the same with the default plan */
+} mica_tune_entry_t;
+
+/* Autotune the plan on a sample batch (same layout and flags as a batch of
+ * mica_dp_align_batch; its output arrays are not written).  For every
+ * 16-base read-length range (1-16, 17-32, ...) with at least 256 pairs in
+ * the sample, up to 65,536 of them are aligned with each candidate plan
+ * covering the range (16 lanes with the fewest rows that cover it and one
+ * more row; 64 lanes with 4, 8 or 16 rows where those cover it), `reps`
+ * timed calls each after one warm-up.  A candidate whose outputs (every
+ * output array, every pair) differ from those of the default plan is
+ * rejected; the fastest remaining one becomes the range's plan.  The
+ * context's plan table is left set to the choices.  Synchronises `stream`.
+ * Writes up to out_cap entries to out (may be NULL) and their number to
+ * *n_out. */
+mica_status_t mica_ctx_autotune(mica_ctx_t ctx, const mica_batch_t *sample, const mica_scoring_t *scoring,
+                                uint32_t flags, void *stream, int32_t reps, mica_tune_entry_t *out,
+                                int32_t out_cap, int32_t *n_out);
+
+/* Save the context's plan table to a JSON file keyed by the device's
+ * architecture name and compute-unit count; load it back into a context on
+ * the same kind of device (another architecture or CU count is refused with
+ * MICA_ERR_INVALID_ARG and leaves the plan unchanged). */
+mica_status_t mica_ctx_save_plan(mica_ctx_t ctx, const char *path);
+mica_status_t mica_ctx_load_plan(mica_ctx_t ctx, const char *path);
 
 /* Counters of the last batch enqueued on ctx (synchronises `stream`). */
 typedef struct {

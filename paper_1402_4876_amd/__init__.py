@@ -16,13 +16,13 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (FORCE_INT32, MAX_READ_LEN, MAX_WIN_LEN, MODE_LOCAL, MODE_SEMIGLOBAL, OUT_CIGAR,
-                   OUT_START, PLAIN_LAUNCH, ST_CIGAR_TRUNC, ST_LEN_LIMIT, ST_READ_OOB, ST_SATURATED,
-                   ST_WIN_OOB, MicaError)
+from ._lib import (FORCE_INT32, MAX_READ_LEN, MAX_WIN_LEN, MODE_LOCAL, MODE_SEMIGLOBAL, NO_GRAPH,
+                   OUT_CIGAR, OUT_START, PLAIN_LAUNCH, ST_CIGAR_TRUNC, ST_LEN_LIMIT, ST_READ_OOB,
+                   ST_SATURATED, ST_WIN_OOB, MicaError)
 from .pack import pack_codes, unpack_words
 
 __all__ = ["Context", "align", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
-           "PLAIN_LAUNCH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "ST_SATURATED",
+           "PLAIN_LAUNCH", "NO_GRAPH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "ST_SATURATED",
            "ST_CIGAR_TRUNC", "ST_LEN_LIMIT", "ST_WIN_OOB", "ST_READ_OOB", "MAX_READ_LEN", "MAX_WIN_LEN"]
 
 
@@ -81,6 +81,31 @@ class Context:
         _lib.check(_lib.load().mica_ctx_read_timing(self._h, ctypes.byref(ms), ctypes.byref(nb)))
         return ms.value, nb.value
 
+    def autotune(self, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None,
+                 scoring=(1, -4, 6, 1), out_start=False, out_cigar=False, cigar_cap=64, force_int32=False,
+                 default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
+                 reads_len=None, reps=3, stream=None):
+        """Tune the plan on a sample batch (same arguments as align); returns one dict per
+        tuned read-length range.  The context keeps the chosen plan."""
+        b, sc, flags, _ = _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring,
+                                      out_start, out_cigar, cigar_cap, force_int32, False, True,
+                                      default_mode, max_read_len, max_win_len, ref_len, reads_len, None,
+                                      outputs=False)
+        cap = 64
+        entries = (_lib.TuneEntry * cap)()
+        n_out = ctypes.c_int32()
+        _lib.check(_lib.load().mica_ctx_autotune(self._h, ctypes.byref(b), ctypes.byref(sc), flags,
+                                                 _stream_handle(stream), int(reps), entries, cap,
+                                                 ctypes.byref(n_out)))
+        return [{f: getattr(entries[i], f) for f, _ in _lib.TuneEntry._fields_ if f != "pad_"}
+                for i in range(n_out.value)]
+
+    def save_plan(self, path):
+        _lib.check(_lib.load().mica_ctx_save_plan(self._h, str(path).encode()))
+
+    def load_plan(self, path):
+        _lib.check(_lib.load().mica_ctx_load_plan(self._h, str(path).encode()))
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.load().mica_ctx_destroy(self._h)
@@ -101,20 +126,9 @@ def pack_2bit(codes, stream=None):
     return words
 
 
-def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, scoring=(1, -4, 6, 1),
-          out_start=False, out_cigar=False, cigar_cap=64, force_int32=False, plain=False,
-          default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
-          reads_len=None, out=None, stream=None):
-    """Align every (read, window) pair on the GPU; returns a dict of tensors.
-
-    ref2b / reads2b: int32 tensors of 2-bit packed bases; win_off / read_off:
-    int64 base offsets; win_len / read_len: int32 lengths; mode: optional uint8
-    per pair (0 semi-global, 1 local).  Outputs: score, read_end, ref_end,
-    status and, when requested, read_start, ref_start, cigar, n_cigar.
-    ``max_read_len`` / ``max_win_len`` default to the batch maxima (one host
-    synchronisation).  The call is asynchronous on ``stream``.
-    """
-    lib = _lib.load()
+def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring, out_start, out_cigar,
+                cigar_cap, force_int32, plain, graph, default_mode, max_read_len, max_win_len, ref_len,
+                reads_len, out, outputs=True):
     ref2b = _dev(ref2b, torch.int32, "ref2b")
     reads2b = _dev(reads2b, torch.int32, "reads2b")
     win_off = _dev(win_off, torch.int64, "win_off")
@@ -134,7 +148,7 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
         max_win_len = int(win_len.max().item()) if n else 0
     dev = win_off.device
     want_start = out_start or out_cigar
-    if out is None:
+    if out is None and outputs:
         out = {
             "score": torch.empty(n, dtype=torch.int32, device=dev),
             "read_end": torch.empty(n, dtype=torch.int32, device=dev),
@@ -147,6 +161,7 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
         if out_cigar:
             out["cigar"] = torch.empty((n, cigar_cap), dtype=torch.int32, device=dev)
             out["n_cigar"] = torch.empty(n, dtype=torch.int32, device=dev)
+    out = out if out is not None else {}
     b = _lib.Batch()
     b.ref2b = _ptr(ref2b)
     b.ref_len = int(ref_len) if ref_len is not None else ref2b.numel() * 16
@@ -161,21 +176,41 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
     b.n_pairs = n
     b.max_read_len = int(max_read_len)
     b.max_win_len = int(max_win_len)
-    b.score = _ptr(out["score"])
-    b.read_end = _ptr(out["read_end"])
-    b.ref_end = _ptr(out["ref_end"])
+    b.score = _ptr(out.get("score"))
+    b.read_end = _ptr(out.get("read_end"))
+    b.ref_end = _ptr(out.get("ref_end"))
     b.read_start = _ptr(out.get("read_start"))
     b.ref_start = _ptr(out.get("ref_start"))
     b.cigar = _ptr(out.get("cigar"))
     b.cigar_cap = int(cigar_cap) if out_cigar else 0
     b.n_cigar = _ptr(out.get("n_cigar"))
-    b.status = _ptr(out["status"])
+    b.status = _ptr(out.get("status"))
     a_, b_, o_, e_ = (int(x) for x in scoring)
     sc = _lib.Scoring(a_, b_, o_, e_)
     flags = (OUT_START if out_start else 0) | (OUT_CIGAR if out_cigar else 0) | \
-        (FORCE_INT32 if force_int32 else 0) | (PLAIN_LAUNCH if plain else 0)
-    _lib.check(lib.mica_dp_align_batch(ctx.handle, ctypes.byref(b), ctypes.byref(sc), flags,
-                                       _stream_handle(stream)))
+        (FORCE_INT32 if force_int32 else 0) | (PLAIN_LAUNCH if plain else 0) | (0 if graph else NO_GRAPH)
+    return b, sc, flags, out
+
+
+def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, scoring=(1, -4, 6, 1),
+          out_start=False, out_cigar=False, cigar_cap=64, force_int32=False, plain=False, graph=True,
+          default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
+          reads_len=None, out=None, stream=None):
+    """Align every (read, window) pair on the GPU; returns a dict of tensors.
+
+    ref2b / reads2b: int32 tensors of 2-bit packed bases; win_off / read_off:
+    int64 base offsets; win_len / read_len: int32 lengths; mode: optional uint8
+    per pair (0 semi-global, 1 local).  Outputs: score, read_end, ref_end,
+    status and, when requested, read_start, ref_start, cigar, n_cigar.
+    ``max_read_len`` / ``max_win_len`` default to the batch maxima (one host
+    synchronisation).  ``graph=False`` enqueues the kernels one by one
+    instead of as one HIP graph.  The call is asynchronous on ``stream``.
+    """
+    b, sc, flags, out = _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring,
+                                    out_start, out_cigar, cigar_cap, force_int32, plain, graph, default_mode,
+                                    max_read_len, max_win_len, ref_len, reads_len, out)
+    _lib.check(_lib.load().mica_dp_align_batch(ctx.handle, ctypes.byref(b), ctypes.byref(sc), flags,
+                                               _stream_handle(stream)))
     return out
 
 

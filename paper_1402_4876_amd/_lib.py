@@ -21,6 +21,7 @@ OUT_START = 1 << 0
 OUT_CIGAR = 1 << 1
 FORCE_INT32 = 1 << 8
 PLAIN_LAUNCH = 1 << 9
+NO_GRAPH = 1 << 10
 
 ST_SATURATED = 1 << 0
 ST_CIGAR_TRUNC = 1 << 1
@@ -34,7 +35,7 @@ MAX_WIN_LEN = 8192
 
 EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_pack_2bit",
            "mica_ctx_set_plan", "mica_ctx_last_stats", "mica_ctx_set_timing", "mica_ctx_read_timing",
-           "mica_last_error")
+           "mica_ctx_autotune", "mica_ctx_save_plan", "mica_ctx_load_plan", "mica_last_error")
 
 
 class Scoring(ctypes.Structure):
@@ -62,6 +63,13 @@ class BatchStats(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("n_saturated", ctypes.c_int64), ("n_waves", ctypes.c_int64),
                 ("scratch_bytes", ctypes.c_int64)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("m_lo", ctypes.c_int32), ("m_hi", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("rows", ctypes.c_int32), ("n_pairs", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("n_rejected", ctypes.c_int32), ("pad_", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -93,6 +101,13 @@ def load():
     lib.mica_ctx_set_timing.restype = ctypes.c_int
     lib.mica_ctx_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.mica_ctx_read_timing.restype = ctypes.c_int
+    lib.mica_ctx_autotune.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), u32, P, i32,
+                                       ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)]
+    lib.mica_ctx_autotune.restype = ctypes.c_int
+    lib.mica_ctx_save_plan.argtypes = [P, ctypes.c_char_p]
+    lib.mica_ctx_save_plan.restype = ctypes.c_int
+    lib.mica_ctx_load_plan.argtypes = [P, ctypes.c_char_p]
+    lib.mica_ctx_load_plan.restype = ctypes.c_int
     lib.mica_last_error.argtypes = []
     lib.mica_last_error.restype = ctypes.c_char_p
     _lib = lib

@@ -11,11 +11,18 @@ constexpr int kMaxM = 1024;  // longest read (rows)
 constexpr int kMaxN = 8192;  // longest window (columns)
 
 // Kernel classes: class c < 16 runs 16 lanes per pair with c+1 read rows per
-// lane (reads up to 16*(c+1) bases); class 16 runs a whole wave (64 lanes)
-// with 16 rows per lane (reads up to 1024 bases).
-constexpr int kNumClasses = 17;
+// lane (reads up to 16*(c+1) bases); classes 16, 17 and 18 run a whole wave
+// (64 lanes) with 16, 4 and 8 rows per lane (reads up to 1024, 256 and 512
+// bases).  The default plan uses classes 0-16; 17 and 18 are alternatives a
+// tuned plan may pick.
+constexpr int kNumClasses = 19;
 __host__ __device__ constexpr int class_lanes(int c) { return c < 16 ? 16 : 64; }
-__host__ __device__ constexpr int class_rows(int c) { return c < 16 ? c + 1 : 16; }
+__host__ __device__ constexpr int class_rows(int c) { return c < 16 ? c + 1 : (c == 16 ? 16 : (c == 17 ? 4 : 8)); }
+// class of (lanes, rows), or -1
+__host__ __device__ constexpr int class_of(int lanes, int rows) {
+  return lanes == 16 ? (rows >= 1 && rows <= 16 ? rows - 1 : -1)
+                     : (lanes == 64 ? (rows == 16 ? 16 : (rows == 4 ? 17 : (rows == 8 ? 18 : -1))) : -1);
+}
 
 // Arithmetic kinds: packed 16-bit (two pairs per 32-bit register), packed
 // 16-bit with a run-time saturation check, and 32-bit.

@@ -167,7 +167,7 @@ __device__ __forceinline__ int base_at(const MICA_GLOBAL uint32_t* __restrict__ 
 // variant spills: 5 waves <= 102 VGPRs, 4 <= 128, 3 <= 170, 2 <= 256.
 __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool dir) {
   const int r = class_rows(cls);
-  if (class_lanes(cls) == 64) return 2;
+  if (class_lanes(cls) == 64 && r == 16) return 2;
   if (kind == kK32) {
     if (mode == 0) return r <= 8 ? 5 : (r <= 11 ? 4 : 3);
     return dir ? (r <= 5 ? 5 : (r <= 8 ? 4 : (r <= 12 ? 3 : 2))) : (r <= 6 ? 5 : (r <= 10 ? 4 : 3));

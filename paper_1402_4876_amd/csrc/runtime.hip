@@ -5,69 +5,24 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
 
+#include "ctx.h"
 #include "dp_common.h"
 #include "mica_dp.h"
 
 using namespace mica;
 
-namespace {
-
+namespace mica {
 thread_local std::string g_last_error;
-
 mica_status_t fail(mica_status_t st, const std::string& msg) {
   g_last_error = msg;
   return st;
 }
-
-#define HIP_TRY(expr)                                                                 \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess)                                                             \
-      return fail(MICA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
-  } while (0)
-
-constexpr int kParamRing = 32;
-constexpr size_t kDefaultWorkspace = size_t(8) << 30;
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-}  // namespace
-
-struct mica_ctx {
-  int device = 0;
-  size_t ws_cap = kDefaultWorkspace;
-  int n_cu = 256;
-  int occ_blocks[2] = {1, 1};  // resident blocks per CU of the persistent kernel
-  // device memory
-  Params* d_params = nullptr;     // ring of kParamRing parameter blocks
-  uint32_t* d_small = nullptr;    // bucket tables and counters
-  uint8_t* d_class = nullptr;     // class_of_m
-  uint32_t* d_pairs = nullptr;    // bucket_of | sorted | rerun
-  int64_t pair_cap = 0;
-  uint8_t* d_scratch = nullptr;
-  size_t scratch_cap = 0;
-  // host state
-  Params* h_params = nullptr;     // pinned ring
-  hipEvent_t ev[kParamRing] = {};
-  bool ev_used[kParamRing] = {};
-  int ring_pos = 0;
-  uint8_t class_of_m[kMaxM + 1];
-  uint32_t qorder[kNumBuckets];
-  uint32_t persist_q[3] = {0, 0, 0};
-  bool class_dirty = true;
-  // fill-kernel timing
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-  // last batch
-  int64_t last_pairs = 0;
-  int last_slots = 0;
-  size_t last_scratch = 0;
-};
+}  // namespace mica
 
 namespace {
 
@@ -90,10 +45,7 @@ double bucket_cost(int b) {
 }
 
 void default_plan(mica_ctx* c) {
-  for (int m = 0; m <= kMaxM; ++m) {
-    if (m <= 256) c->class_of_m[m] = (uint8_t)(m == 0 ? 0 : (m + 15) / 16 - 1);
-    else c->class_of_m[m] = 16;
-  }
+  for (int m = 0; m <= kMaxM; ++m) c->class_of_m[m] = (uint8_t)default_class_of(m);
   c->class_dirty = true;
 }
 
@@ -146,6 +98,113 @@ hipError_t launch(KernelFn fn, unsigned blocks, unsigned threads, size_t shmem, 
   return hipLaunchKernel((const void*)fn, dim3(blocks), dim3(threads), args, shmem, s);
 }
 
+// One kernel launch of a batch; `fill` marks the launches the timing events
+// bracket.
+struct Launch {
+  KernelFn fn;
+  unsigned grid, block;
+  size_t shmem;
+  bool fill;
+};
+
+hipKernelNodeParams node_params(const Launch& l, void** args) {
+  hipKernelNodeParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.func = (void*)l.fn;
+  p.gridDim = dim3(l.grid);
+  p.blockDim = dim3(l.block);
+  p.sharedMemBytes = (unsigned)l.shmem;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return p;
+}
+
+// Build the graph of a launch sequence: a chain of kernel nodes, with event
+// record nodes around the fill launches when timing is on.
+mica_status_t build_graph(mica_ctx* c, const std::vector<Launch>& seq, bool timing, const Params* dp,
+                          hipEvent_t t0, hipEvent_t t1, mica_ctx::Graph* out) {
+  mica_ctx::Graph g;
+  HIP_TRY(hipGraphCreate(&g.graph, 0));
+  hipGraphNode_t prev = nullptr;
+  auto add_event = [&](hipEvent_t e, hipGraphNode_t* node) -> hipError_t {
+    hipError_t err = hipGraphAddEventRecordNode(node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0, e);
+    if (err == hipSuccess) prev = *node;
+    return err;
+  };
+  bool began = false;
+  for (size_t i = 0; i < seq.size(); ++i) {
+    if (timing && seq[i].fill && !began) {
+      HIP_TRY(add_event(t0, &g.ev_begin));
+      began = true;
+    }
+    void* args[] = {(void*)&dp};
+    hipKernelNodeParams p = node_params(seq[i], args);
+    hipGraphNode_t node;
+    HIP_TRY(hipGraphAddKernelNode(&node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+    g.kernel_nodes.push_back(node);
+    prev = node;
+    const bool last_fill = seq[i].fill && (i + 1 == seq.size() || !seq[i + 1].fill);
+    if (timing && last_fill) HIP_TRY(add_event(t1, &g.ev_end));
+  }
+  if (timing && !began) {  // no fill launch: the two events are adjacent
+    HIP_TRY(add_event(t0, &g.ev_begin));
+    HIP_TRY(add_event(t1, &g.ev_end));
+  }
+  HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  c->graph_builds++;
+  *out = g;
+  return MICA_OK;
+}
+
+mica_status_t run_sequence(mica_ctx* c, const std::vector<Launch>& seq, const Params* dp, hipStream_t stream,
+                           bool use_graph, hipEvent_t t0, hipEvent_t t1) {
+  const bool timing = t0 != nullptr;
+  if (!use_graph) {
+    bool began = false;
+    for (size_t i = 0; i < seq.size(); ++i) {
+      if (timing && seq[i].fill && !began) {
+        HIP_TRY(hipEventRecord(t0, stream));
+        began = true;
+      }
+      HIP_TRY(launch(seq[i].fn, seq[i].grid, seq[i].block, seq[i].shmem, stream, dp));
+      if (timing && seq[i].fill && (i + 1 == seq.size() || !seq[i + 1].fill)) HIP_TRY(hipEventRecord(t1, stream));
+    }
+    if (timing && !began) {
+      HIP_TRY(hipEventRecord(t0, stream));
+      HIP_TRY(hipEventRecord(t1, stream));
+    }
+    return MICA_OK;
+  }
+  std::vector<uint64_t> key;
+  key.push_back(timing ? 1 : 0);
+  for (const Launch& l : seq) {
+    key.push_back((uint64_t)(uintptr_t)l.fn);
+    key.push_back(((uint64_t)l.block << 32) | (uint64_t)l.shmem);
+    key.push_back(l.fill ? 1 : 0);
+  }
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    mica_ctx::Graph g;
+    mica_status_t st = build_graph(c, seq, timing, dp, t0, t1, &g);
+    if (st != MICA_OK) return st;
+    it = c->graphs.emplace(std::move(key), g).first;
+  } else {
+    mica_ctx::Graph& g = it->second;
+    for (size_t i = 0; i < seq.size(); ++i) {
+      void* args[] = {(void*)&dp};
+      hipKernelNodeParams p = node_params(seq[i], args);
+      HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.kernel_nodes[i], &p));
+    }
+    if (timing) {
+      HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g.exec, g.ev_begin, t0));
+      HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g.exec, g.ev_end, t1));
+    }
+  }
+  HIP_TRY(hipGraphLaunch(it->second.exec, stream));
+  c->graph_launches++;
+  return MICA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -165,6 +224,11 @@ mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   c->n_cu = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  {
+    const size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch.resize(colon);
+  }
   const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
   for (int d = 0; d < 2; ++d) {
     int nb = 0;
@@ -219,6 +283,10 @@ mica_status_t mica_ctx_destroy(mica_ctx_t c) {
     (void)hipEventDestroy(pr.second);
   }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& kv : c->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
   delete c;
   return MICA_OK;
 }
@@ -226,10 +294,8 @@ mica_status_t mica_ctx_destroy(mica_ctx_t c) {
 mica_status_t mica_ctx_set_plan(mica_ctx_t c, int32_t m_lo, int32_t m_hi, int32_t lanes, int32_t rows) {
   if (!c) return fail(MICA_ERR_INVALID_ARG, "ctx is NULL");
   if (m_lo < 1 || m_hi > kMaxM || m_lo > m_hi) return fail(MICA_ERR_INVALID_ARG, "bad read-length range");
-  int cls;
-  if (lanes == 16 && rows >= 1 && rows <= 16) cls = rows - 1;
-  else if (lanes == 64 && rows == 16) cls = 16;
-  else return fail(MICA_ERR_INVALID_ARG, "unsupported (lanes, rows)");
+  const int cls = class_of(lanes, rows);
+  if (cls < 0) return fail(MICA_ERR_INVALID_ARG, "unsupported (lanes, rows)");
   if (lanes * rows < m_hi) return fail(MICA_ERR_INVALID_ARG, "lanes * rows must cover m_hi");
   for (int m = m_lo; m <= m_hi; ++m) c->class_of_m[m] = (uint8_t)cls;
   HIP_TRY(hipSetDevice(c->device));
@@ -247,7 +313,7 @@ mica_status_t mica_pack_2bit(const uint8_t* codes, int64_t n_bases, uint32_t* wo
 mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mica_scoring_t* s,
                                   uint32_t flags, void* stream_) {
   if (!c || !b || !s) return fail(MICA_ERR_INVALID_ARG, "NULL ctx, batch or scoring");
-  const uint32_t known = MICA_OUT_START | MICA_OUT_CIGAR | MICA_FORCE_INT32 | MICA_PLAIN_LAUNCH;
+  const uint32_t known = MICA_OUT_START | MICA_OUT_CIGAR | MICA_FORCE_INT32 | MICA_PLAIN_LAUNCH | MICA_NO_GRAPH;
   if (flags & ~known) return fail(MICA_ERR_INVALID_ARG, "unknown flag bits");
   if (s->match < 1 || s->match > 4096 || s->mismatch > 0 || s->mismatch < -4096 || s->gap_open < 0 ||
       s->gap_open > 4096 || s->gap_extend < 1 || s->gap_extend > 4096)
@@ -351,25 +417,20 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   const unsigned pblocks = (unsigned)((b->n_pairs + 255) / 256);
   const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
   const unsigned fblocks = (unsigned)(slots / kWavesPerBlock);
-  HIP_TRY(launch(K.zero, 1, 256, 0, stream, dp));
-  HIP_TRY(launch(K.plan, pblocks, 256, 0, stream, dp));
-  HIP_TRY(launch(K.scan, 1, 64, 0, stream, dp));
-  HIP_TRY(launch(K.scatter, pblocks, 256, 0, stream, dp));
+  std::vector<Launch> seq;
+  seq.push_back({K.zero, 1, 256, 0, false});
+  seq.push_back({K.plan, pblocks, 256, 0, false});
+  seq.push_back({K.scan, 1, 64, 0, false});
+  seq.push_back({K.scatter, pblocks, 256, 0, false});
 
   const bool forced = flags & MICA_FORCE_INT32;
   const bool any_local = b->mode ? true : b->default_mode == 1;
   const bool any_sg = b->mode ? true : b->default_mode == 0;
   const bool may_sat = !forced && !int16_always_safe(max_m, max_n, *s, any_local, any_sg);
   const bool plain = flags & MICA_PLAIN_LAUNCH;
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  if (c->timing) {
-    HIP_TRY(take_event(c, &t0));
-    HIP_TRY(take_event(c, &t1));
-    HIP_TRY(hipEventRecord(t0, stream));
-  }
   if (!plain && !forced) {
-    if (any_sg) HIP_TRY(launch(K.persistent[d][0], fblocks, 256, shmem, stream, dp));
-    if (any_local) HIP_TRY(launch(K.persistent[d][1], fblocks, 256, shmem, stream, dp));
+    if (any_sg) seq.push_back({K.persistent[d][0], fblocks, 256, shmem, true});
+    if (any_local) seq.push_back({K.persistent[d][1], fblocks, 256, shmem, true});
   }
   // plain launches: every bucket in plain mode, else the buckets the
   // persistent kernel does not serve
@@ -384,15 +445,19 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
         if ((md == 1 && !any_local) || (md == 0 && !any_sg)) continue;
         const int bk = bucket_id(kind, cls, md);
         if (!plain && persistent_bucket(bk)) continue;
-        HIP_TRY(launch(K.bucket[d][bk], fblocks, 256, shmem, stream, dp));
+        seq.push_back({K.bucket[d][bk], fblocks, 256, shmem, true});
       }
     }
   }
-  if (may_sat) HIP_TRY(launch(K.rerun[d], fblocks, 256, shmem, stream, dp));
+  if (may_sat) seq.push_back({K.rerun[d], fblocks, 256, shmem, true});
+  hipEvent_t t0 = nullptr, t1 = nullptr;
   if (c->timing) {
-    HIP_TRY(hipEventRecord(t1, stream));
-    c->ev_pending.emplace_back(t0, t1);
+    HIP_TRY(take_event(c, &t0));
+    HIP_TRY(take_event(c, &t1));
   }
+  st = run_sequence(c, seq, dp, stream, !(flags & MICA_NO_GRAPH), t0, t1);
+  if (st != MICA_OK) return st;
+  if (c->timing) c->ev_pending.emplace_back(t0, t1);
   c->last_pairs = b->n_pairs;
   c->last_slots = (int)slots;
   c->last_scratch = (size_t)slots * slot_bytes;

@@ -30,7 +30,8 @@ def test_struct_layout_matches_header(tmp_path):
     """ctypes mirrors of the C structs: same size and field offsets as gcc gives."""
     import subprocess
     from paper_1402_4876_amd import _lib
-    structs = {"mica_batch_t": _lib.Batch, "mica_scoring_t": _lib.Scoring, "mica_batch_stats_t": _lib.BatchStats}
+    structs = {"mica_batch_t": _lib.Batch, "mica_scoring_t": _lib.Scoring, "mica_batch_stats_t": _lib.BatchStats,
+               "mica_tune_entry_t": _lib.TuneEntry}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mica_dp.h"', 'int main(void) {']
     for cname, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -58,6 +59,11 @@ def test_invalid_arguments_fail_before_any_device_call():
     assert lib.mica_pack_2bit(None, -1, None, None) == -1
     assert lib.mica_pack_2bit(None, 10, None, None) == -1
     assert lib.mica_ctx_set_plan(None, 1, 10, 16, 1) == -1
+    n_out = ctypes.c_int32(7)
+    assert lib.mica_ctx_autotune(None, ctypes.byref(b), ctypes.byref(s), 0, None, 1, None, 0,
+                                 ctypes.byref(n_out)) == -1
+    assert lib.mica_ctx_save_plan(None, b"/nonexistent/plan.json") == -1
+    assert lib.mica_ctx_load_plan(None, b"/nonexistent/plan.json") == -1
     assert lib.mica_ctx_destroy(None) == 0
     h = ctypes.c_void_p()
     rc = lib.mica_ctx_create(-1, 0, ctypes.byref(h))
