@@ -120,6 +120,100 @@ def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
     return base, parity
 
 
+def serving_bench(n_per_rate=2000, warmup=200, pool_size=32, slots=4, fracs=(0.3, 0.6, 0.9)):
+    """Open-loop serving of config-4 requests: a 3 Gbp reference resident on the
+    GPU, requests of 1..10,000 reads of {100, 150, 250} bp (windows 1.5 m + 64,
+    semi-global, full outputs) arriving as a Poisson stream at 0.3 / 0.6 / 0.9
+    of the saturated request rate (measured closed-loop first), through the
+    continuous-batching server and through the FIFO baseline (one request per
+    batch, one slot).  Latency = finish - scheduled arrival, on the server."""
+    import synth
+    import paper_1402_4876_amd as mica
+    from paper_1402_4876_amd.pack import pack_codes
+    ref_len = 3_000_000_000
+    t0 = time.time()
+    ref = synth.serving_reference(ref_len)
+    pool = []
+    for i in range(pool_size):
+        r = synth.serving_request(ref, ref_len, i)
+        pool.append((pack_codes(r.reads), r.read_off.astype(np.uint64), r.read_len.astype(np.int32),
+                     r.win_off.astype(np.uint64), r.win_len.astype(np.int32), int(r.cells())))
+    log("serving: reference and %d-request pool in %.1fs" % (pool_size, time.time() - t0))
+
+    def submit(srv, rid, arrival):
+        w, ro, rl, wo, wl, _ = pool[rid % pool_size]
+        srv.submit(rid, w, ro, rl, wo, wl, arrival=arrival)
+
+    def drain(srv, pending, until_empty):
+        while pending:
+            for i in srv.poll():
+                srv.fetch(i)
+                pending.discard(i)
+            if not until_empty:
+                return
+            time.sleep(0.0002)
+
+    def closed_loop(srv, n, base):
+        pending = set()
+        t = srv.now()
+        for k in range(n):
+            submit(srv, base + k, t)
+            pending.add(base + k)
+        drain(srv, pending, True)
+        return n / (srv.now() - t)
+
+    def open_loop(srv, rate, n_warm, n, base, seed):
+        arr = synth.poisson_arrivals(rate, n_warm + n, seed_key=seed)
+        pending = set()
+        start = srv.now() + 0.01
+        for k in range(n_warm + n):
+            if k == n_warm:
+                drain(srv, pending, True)
+                srv.reset_stats()
+            ts = start + arr[k]
+            while True:
+                dt = ts - srv.now()
+                if dt <= 0:
+                    break
+                if dt > 0.0005:
+                    drain(srv, pending, False)
+                    time.sleep(min(dt - 0.0003, 0.002))
+            submit(srv, base + k, ts)
+            pending.add(base + k)
+        drain(srv, pending, True)
+        st = srv.stats()
+        return {"rate_rps": round(rate, 1), "p50_ms": round(st["p50_s"] * 1e3, 3),
+                "p99_ms": round(st["p99_s"] * 1e3, 3), "gcups": round(st["gcups"], 1)}
+
+    out = {"reference_bases": ref_len, "requests_per_rate": n_per_rate, "warmup_requests": warmup,
+           "request_pool": pool_size, "mean_cells_per_request": round(float(np.mean([p[5] for p in pool])), 1)}
+    srv = mica.Server(ref, ref_len, slots=slots)
+    try:
+        closed_loop(srv, 2 * pool_size, 10_000_000)
+        lam = closed_loop(srv, 8 * pool_size, 20_000_000)
+        out["lambda_max_rps"] = round(lam, 1)
+        out["batching"] = {"slots": slots, "rates": []}
+        for i, f in enumerate(fracs):
+            r = open_loop(srv, f * lam, warmup, n_per_rate, 30_000_000 + i * 1_000_000, seed=i)
+            r["frac_of_max"] = f
+            out["batching"]["rates"].append(r)
+            log("serving batching %.1f x max: %s" % (f, r))
+    finally:
+        srv.close()
+    fifo = mica.Server(ref, ref_len, slots=1, fifo=True)
+    try:
+        out["fifo_baseline"] = {"slots": 1, "rates": []}
+        out["fifo_baseline"]["lambda_max_rps"] = round(closed_loop(fifo, 4 * pool_size, 40_000_000), 1)
+        for i, f in enumerate(fracs):
+            r = open_loop(fifo, f * lam, warmup, n_per_rate, 50_000_000 + i * 1_000_000, seed=i)
+            r["frac_of_max"] = f
+            out["fifo_baseline"]["rates"].append(r)
+            log("serving fifo %.1f x max: %s" % (f, r))
+    finally:
+        fifo.close()
+    return out
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """A device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
     gives the counter-to-bytes factor used for the DP kernel's HBM traffic."""
@@ -142,6 +236,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=0, help="override the pair count (testing only)")
     ap.add_argument("--plain", action="store_true", help="per-bucket launches instead of the persistent one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving (request stream) measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -230,6 +326,8 @@ def main():
         "saturated_pairs": int(stats["n_saturated"]),
         "resident_waves": int(stats["n_waves"]),
     }
+    if not args.no_serving:
+        res["serving"] = serving_bench(n_per_rate=args.serve_requests, warmup=max(args.serve_requests // 10, 20))
     if not args.no_cpu_baseline:
         base, parity = cpu_baseline(batch, host, want_trace)
         res["cpu_baseline"] = base

@@ -215,6 +215,66 @@ mica_status_t mica_ctx_last_stats(mica_ctx_t ctx, void *stream, mica_batch_stats
 mica_status_t mica_ctx_set_timing(mica_ctx_t ctx, int enable);
 mica_status_t mica_ctx_read_timing(mica_ctx_t ctx, double *fill_ms, int64_t *n_batches);
 
+/* ---- Serving ------------------------------------------------------------
+ * A server keeps the reference resident on one GPU and aligns requests of
+ * reads submitted from the host (the paper's host controller that feeds the
+ * card large batches and keeps it busy, architecture section).  A worker
+ * thread packs every queued request that fits (oldest first; up to 65,536
+ * reads per batch) into the next free in-flight slot; each slot has its own
+ * HIP stream, library context and staging, so copies and kernels of
+ * different slots overlap (continuous batching).  Requests whose staging
+ * would not fit wait in the queue (admission by the slots' HBM budget).
+ * Results are exact and identical to mica_dp_align_batch on the same pairs,
+ * whatever else shares the batch.  All server calls are thread-safe. */
+typedef struct mica_server *mica_server_t;
+
+/* flag of mica_server_create: one request per batch (a FIFO baseline
+ * without batching; use with max_inflight_slots = 1 for no overlap) */
+enum { MICA_SERVE_FIFO = 1u << 16 };
+
+/* Create a server on `hip_device`: uploads the 2-bit reference (host words,
+ * ref_len bases) once; `hbm_budget_bytes` (0 = 24 GiB) bounds the device
+ * memory of reference, slots' staging and their contexts' scratch;
+ * `max_inflight_slots` in 1..16; `flags`: mica_dp_align_batch flags
+ * (MICA_OUT_CIGAR keeps 64 CIGAR runs per read) and MICA_SERVE_FIFO. */
+mica_status_t mica_server_create(int hip_device, const uint32_t *host_ref2b, uint64_t ref_len,
+                                 size_t hbm_budget_bytes, int max_inflight_slots,
+                                 const mica_scoring_t *scoring, uint32_t flags, mica_server_t *out);
+
+/* Seconds on the server's clock (a steady clock started at creation). */
+mica_status_t mica_server_now(mica_server_t server, double *t);
+
+/* Queue request `request_id` (unique among unfetched requests) of n reads:
+ * read p is host_reads2b[read_off[p], +read_len[p]) (bases, 2-bit host
+ * words), aligned against ref[win_off[p], +win_len[p]) in mode[p] (NULL: all
+ * semi-global).  The arrays are copied before the call returns.
+ * `arrival_time_s` on the server clock is the time latency is measured from
+ * (< 0: now).  MICA_ERR_LIMIT for requests over 65,536 reads. */
+mica_status_t mica_server_submit(mica_server_t server, uint64_t request_id, const uint32_t *host_reads2b,
+                                 const uint64_t *read_off, const int32_t *read_len, const uint64_t *win_off,
+                                 const int32_t *win_len, const uint8_t *mode, int64_t n,
+                                 double arrival_time_s);
+
+/* Ids of requests finished since the last poll (up to cap); *n_done of them. */
+mica_status_t mica_server_poll(mica_server_t server, uint64_t *done_ids, int64_t cap, int64_t *n_done);
+
+/* Copy a finished request's outputs (n entries each, as mica_dp_align_batch;
+ * cigar: n * cigar_cap words, at most 64 runs kept; any pointer may be NULL)
+ * and forget the request.  MICA_ERR_BUSY while it is not finished. */
+mica_status_t mica_server_fetch(mica_server_t server, uint64_t request_id, int32_t *score,
+                                int32_t *read_start, int32_t *read_end, int32_t *ref_start, int32_t *ref_end,
+                                uint32_t *cigar, int32_t cigar_cap, int32_t *n_cigar, uint32_t *status);
+
+/* Latency percentiles (finish - arrival, seconds) of the requests finished
+ * since creation or the last reset, and their cells per second (GCUPS) over
+ * the span from the first arrival to the last finish.  MICA_ERR_HIP if a
+ * batch failed (its requests finish with MICA_ST_INTERNAL). */
+mica_status_t mica_server_stats(mica_server_t server, double *p50_s, double *p99_s, double *gcups);
+mica_status_t mica_server_reset_stats(mica_server_t server);
+
+/* Finish the queued work, stop the worker and free everything. */
+mica_status_t mica_server_destroy(mica_server_t server);
+
 /* Text of the last non-OK status returned on this host thread. */
 const char *mica_last_error(void);
 

@@ -20,8 +20,9 @@ from ._lib import (FORCE_INT32, MAX_READ_LEN, MAX_WIN_LEN, MODE_LOCAL, MODE_SEMI
                    OUT_CIGAR, OUT_START, PLAIN_LAUNCH, ST_CIGAR_TRUNC, ST_LEN_LIMIT, ST_READ_OOB,
                    ST_SATURATED, ST_WIN_OOB, MicaError)
 from .pack import pack_codes, unpack_words
+from .serve import Server
 
-__all__ = ["Context", "align", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
+__all__ = ["Context", "Server", "align", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
            "PLAIN_LAUNCH", "NO_GRAPH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "ST_SATURATED",
            "ST_CIGAR_TRUNC", "ST_LEN_LIMIT", "ST_WIN_OOB", "ST_READ_OOB", "MAX_READ_LEN", "MAX_WIN_LEN"]
 

@@ -22,6 +22,7 @@ OUT_CIGAR = 1 << 1
 FORCE_INT32 = 1 << 8
 PLAIN_LAUNCH = 1 << 9
 NO_GRAPH = 1 << 10
+SERVE_FIFO = 1 << 16
 
 ST_SATURATED = 1 << 0
 ST_CIGAR_TRUNC = 1 << 1
@@ -35,7 +36,9 @@ MAX_WIN_LEN = 8192
 
 EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_pack_2bit",
            "mica_ctx_set_plan", "mica_ctx_last_stats", "mica_ctx_set_timing", "mica_ctx_read_timing",
-           "mica_ctx_autotune", "mica_ctx_save_plan", "mica_ctx_load_plan", "mica_last_error")
+           "mica_ctx_autotune", "mica_ctx_save_plan", "mica_ctx_load_plan", "mica_server_create",
+           "mica_server_now", "mica_server_submit", "mica_server_poll", "mica_server_fetch", "mica_server_stats",
+           "mica_server_reset_stats", "mica_server_destroy", "mica_last_error")
 
 
 class Scoring(ctypes.Structure):
@@ -108,6 +111,18 @@ def load():
     lib.mica_ctx_save_plan.restype = ctypes.c_int
     lib.mica_ctx_load_plan.argtypes = [P, ctypes.c_char_p]
     lib.mica_ctx_load_plan.restype = ctypes.c_int
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.mica_server_create.argtypes = [ctypes.c_int, P, ctypes.c_uint64, sz, ctypes.c_int, ctypes.POINTER(Scoring),
+                                       u32, ctypes.POINTER(P)]
+    lib.mica_server_now.argtypes = [P, D]
+    lib.mica_server_submit.argtypes = [P, ctypes.c_uint64, P, P, P, P, P, P, i64, ctypes.c_double]
+    lib.mica_server_poll.argtypes = [P, P, i64, ctypes.POINTER(i64)]
+    lib.mica_server_fetch.argtypes = [P, ctypes.c_uint64, P, P, P, P, P, P, i32, P, P]
+    lib.mica_server_stats.argtypes = [P, D, D, D]
+    lib.mica_server_reset_stats.argtypes = [P]
+    lib.mica_server_destroy.argtypes = [P]
+    for f in ("create", "now", "submit", "poll", "fetch", "stats", "reset_stats", "destroy"):
+        getattr(lib, "mica_server_" + f).restype = ctypes.c_int
     lib.mica_last_error.argtypes = []
     lib.mica_last_error.restype = ctypes.c_char_p
     _lib = lib

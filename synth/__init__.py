@@ -327,7 +327,7 @@ def serving_request(ref_words, ref_len, req_id, n_reads=None, max_reads=10_000):
     k = int(rng.integers(1, max_reads + 1)) if n_reads is None else int(n_reads)
     mm = rng.choice(np.array(SERVE_LENGTHS, np.int32), k)
     nn = (3 * mm) // 2 + 64
-    win_off = (rng.random(k) * (ref_len - nn + 1)).astype(np.int64)
+    win_off = (rng.random(k) * (ref_len - nn.astype(np.int64) + 1)).astype(np.int64)
     codes, s, e, _ = _draw_reads(rng, lambda pos: base_at_packed(ref_words, pos), win_off,
                                  win_off + nn - mm - 8, mm, lambda idx: win_off[idx] + nn[idx],
                                  0.01, 0.003, "geom", False)

@@ -63,6 +63,16 @@ def test_invalid_arguments_fail_before_any_device_call():
     assert lib.mica_ctx_autotune(None, ctypes.byref(b), ctypes.byref(s), 0, None, 1, None, 0,
                                  ctypes.byref(n_out)) == -1
     assert lib.mica_ctx_save_plan(None, b"/nonexistent/plan.json") == -1
+    hs = ctypes.c_void_p()
+    assert lib.mica_server_create(0, None, 0, 0, 0, ctypes.byref(s), 0, ctypes.byref(hs)) == -1  # 0 slots
+    assert lib.mica_server_create(0, None, 0, 0, 1, ctypes.byref(s), 1 << 20, ctypes.byref(hs)) == -1  # flag
+    assert not hs.value
+    k = ctypes.c_int64()
+    assert lib.mica_server_submit(None, 1, None, None, None, None, None, None, 0, 0.0) == -1
+    assert lib.mica_server_poll(None, None, 0, ctypes.byref(k)) == -1
+    assert lib.mica_server_fetch(None, 1, None, None, None, None, None, None, 0, None, None) == -1
+    assert lib.mica_server_stats(None, None, None, None) == -1
+    assert lib.mica_server_destroy(None) == 0
     assert lib.mica_ctx_load_plan(None, b"/nonexistent/plan.json") == -1
     assert lib.mica_ctx_destroy(None) == 0
     h = ctypes.c_void_p()
