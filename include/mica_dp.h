@@ -6,12 +6,11 @@
  * programming"): reads that few-mismatch search could not place are aligned
  * by DP allowing insertions and deletions (architecture section) against a
  * candidate region of the reference, with the affine gap model of three
- * tables M, I and D
- * holding the best score of an alignment ending in a Match, an Insert or a
- * Delete.  Cell (i,j) of the table depends on (i-1,j-1), (i-1,j) and
- * (i,j-1).  DP is used where indels and soft clipping are needed, hence two
- * modes: semi-global (the whole read against any substring of the window)
- * and local (both ends clipped, Smith-Waterman).
+ * tables M, I and D holding the best score of an alignment ending in a
+ * Match, an Insert or a Delete.  Cell (i,j) of the table depends on
+ * (i-1,j-1), (i-1,j) and (i,j-1).  DP serves reads that need gaps or clipped
+ * ends, hence two modes: semi-global (the whole read against any substring
+ * of the window) and local (both ends clipped, Smith-Waterman).
  *
  * Readings of what the paper leaves open (scores, boundaries, ties, CIGAR):
  *   - scoring: s(x,y) = match if x == y else mismatch; a gap of length L

@@ -13,8 +13,8 @@
  *     a Match (here the diagonal candidate M = H(i-1,j-1)+s), one ending in
  *     an Insert (I, consumes a read base only) and one ending in a Delete
  *     (D, consumes a reference base only); H(i,j) = max(M, I, D);
- *   - DP is used where indels and soft clipping are needed (Methods,
- *     architecture section and DP section), hence two modes: semi-global
+ *   - the method turns to DP for reads that need gaps or clipped ends
+ *     (Methods, architecture section and DP section), hence two modes: semi-global
  *     (whole read against any substring of the window) and local
  *     (Smith-Waterman, both ends free: the clipped ends).
  * The paper gives no scores, boundaries, tie-breaks, or CIGAR rules; the
