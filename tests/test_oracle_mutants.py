@@ -49,12 +49,16 @@ def build_mutant(name):
     old, new = MUTANTS[name]
     text = open(SRC).read()
     assert text.count(old) == 1, name
-    d = tempfile.mkdtemp(prefix="oracle_mut_")
-    c = os.path.join(d, "m.c")
-    so = os.path.join(d, "m.so")
-    open(c, "w").write(text.replace(old, new))
-    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-pthread", c, "-o", so])
-    return ctypes.CDLL(so)
+    # built inside the repository's (git-ignored) build folder, removed again
+    # once loaded
+    base = os.path.join(ROOT, "_build")
+    os.makedirs(base, exist_ok=True)
+    with tempfile.TemporaryDirectory(prefix="oracle_mut_", dir=base) as d:
+        c = os.path.join(d, "m.c")
+        so = os.path.join(d, "m.so")
+        open(c, "w").write(text.replace(old, new))
+        subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-pthread", c, "-o", so])
+        return ctypes.CDLL(so)
 
 
 def _bind(lib):
