@@ -14,6 +14,7 @@ if HERE not in sys.path:
 def pytest_configure(config):
     # temporary files of tests stay inside the repository's git-ignored build folder
     if not config.option.basetemp:
+        os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
         config.option.basetemp = os.path.join(ROOT, "_build", "pytest")
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
