@@ -38,7 +38,7 @@ struct mica_ctx {
   std::string arch;  // gcnArchName of the device
   size_t ws_cap = mica::kDefaultWorkspace;
   int n_cu = 256;
-  int occ_blocks[2] = {1, 1};  // resident blocks per CU of the persistent kernel
+  std::map<const void*, int> occ_cache;  // resident blocks per CU of each fill kernel
   // device memory
   mica::Params* d_params = nullptr;     // ring of kParamRing parameter blocks
   uint32_t* d_small = nullptr;    // bucket tables and counters

@@ -118,6 +118,7 @@ struct Params {
   const uint32_t* qorder;      // [kNumBuckets] bucket served at each queue position
   const uint8_t* class_of_m;   // [kMaxM + 1]
   uint32_t* counters;          // [kNumCounters]
+  uint32_t* bhead;             // [kNumBuckets] next work item of each plain bucket launch
   uint8_t* scratch;            // n_slots * slot_bytes
   uint64_t slot_bytes;         // per resident wave: direction bits + CIGAR staging
   uint64_t dir_bytes;          // direction-bit part of a slot

@@ -174,10 +174,10 @@ __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool d
   }
   const int sat = kind == kK16Sat ? 1 : 0;
   if (mode == 0) {
-    if (dir) return r <= 5 - sat ? 5 : (r <= 9 - sat ? 4 : (r <= 14 - 2 * sat ? 3 : 2));
+    if (dir) return r <= 5 - 2 * sat ? 5 : (r <= 10 - 2 * sat ? 4 : (r <= 15 - 3 * sat ? 3 : 2));
     return r <= 6 - sat ? 5 : (r <= 12 - 3 * sat ? 4 : (r <= 16 - 2 * sat ? 3 : 2));
   }
-  if (dir) return r <= 4 - sat ? 4 : (r <= 8 - sat ? 3 : (r <= 15 ? 2 : 1));
+  if (dir) return r <= 3 - sat ? 5 : (r <= 6 - sat ? 4 : (r <= 10 - 2 * sat ? 3 : (r <= 15 || !sat ? 2 : 1)));
   return r <= 4 - sat ? 5 : (r <= 8 - sat ? 4 : (r <= 12 - sat ? 3 : 2));
 }
 #ifdef MICA_FILL_WAVES
@@ -276,7 +276,9 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   const uint32_t tab_hi = ((uint32_t)sb & 0xFFFFu) | ((uint32_t)sb << 16);
 
   // ---- column 0 ---------------------------------------------------------------
-  T H[R], Tt[R], D[R];
+  // per row: H, and E = the next column's deletion candidate
+  // max(D - e, H - o - e) (D and T = H - o - e are not kept)
+  T H[R], E[R];
   T bb[LOCAL ? R : 1], cc[LOCAL ? R : 1];
   int hv[NP];
 #pragma unroll
@@ -293,12 +295,11 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     }
     if constexpr (NP == 2) {
       H[r] = V::make2(hv[0], hv[1]);
-      Tt[r] = V::make2(hv[0] - oe, hv[1] - oe);
+      E[r] = V::make2(hv[0] - oe, hv[1] - oe);  // D(i,0) is -inf
     } else {
       H[r] = (T)hv[0];
-      Tt[r] = (T)(hv[0] - oe);
+      E[r] = (T)(hv[0] - oe);
     }
-    D[r] = (T)V::kNeg;
   }
   T floor_v = (T)0;
   if constexpr (LOCAL) {
@@ -317,7 +318,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     hmax = V::splat(-32768);
     tmin = V::splat(32767);
 #pragma unroll
-    for (int r = 0; r < R; ++r) tmin = V::vmin(tmin, Tt[r]);
+    for (int r = 0; r < R; ++r) tmin = V::vmin(tmin, E[r]);
   }
   // semi-global best over row m: key (score << 16 | 0xFFFF - j), or (score, j)
   int32_t best_key[NP];
@@ -344,7 +345,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   const T oev = V::splat(oe);
   const T tbound = V::splat(-oe);
   const T negv = (T)V::kNeg;
-  T t_last = Tt[R - 1];
+  T t_last = E[R - 1];  // T of the bottom row, column 0
   T i_last = negv;
   T hdiag_next = (T)0;
   T nn_v = (T)0;
@@ -392,19 +393,21 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         constexpr int r = decltype(rc)::value;
         const T s = (T)__builtin_amdgcn_perm(tab_hi, tab_lo, Q[r] ^ rsel);
         const T x = V::add(hdiag, s);
-        const T dn = V::vmax(V::sub(D[r], ev), Tt[r]);
+        const T dn = E[r];
         const T in = V::vmax(V::sub(iup, ev), tup);
         T h = V::max3(x, dn, in);
         if constexpr (LOCAL) h = V::vmax(h, floor_v);
         const T tn = V::sub(h, oev);
+        const T en = V::vmax(V::sub(dn, ev), tn);
         if constexpr (DIR) {
           // sign set: kind 0 diagonal loses, 1 deletion loses, 2 deletion
-          // extends, 3 insertion extends
+          // extends into the NEXT column (read by the walker one step back),
+          // 3 insertion extends
           // the first row of a word takes the whole sign bytes, each later
           // row keeps the bits below it and overwrites the rest (bits above
           // the word's last row are copies of that row and never read)
           const uint32_t s01 = __builtin_amdgcn_perm((uint32_t)V::sub(dn, h), (uint32_t)V::sub(x, h), V::kSignSel);
-          const uint32_t s23 = __builtin_amdgcn_perm((uint32_t)V::sub(tup, in), (uint32_t)V::sub(Tt[r], dn), V::kSignSel);
+          const uint32_t s23 = __builtin_amdgcn_perm((uint32_t)V::sub(tup, in), (uint32_t)V::sub(tn, en), V::kSignSel);
           constexpr int w = (r >> 3) * 2;
           if constexpr ((r & 7) == 0) {
             acc[w] = s01;
@@ -433,8 +436,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         }
         hdiag = H[r];
         H[r] = h;
-        Tt[r] = tn;
-        D[r] = dn;
+        E[r] = en;
         tup = tn;
         iup = in;
 #if MICA_ROW_SCHED_BARRIER
@@ -443,8 +445,8 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 #endif
       });
       i_last = iup;
+      t_last = tup;
     }
-    t_last = Tt[R - 1];
     if (((t + 2) & (kRing / 2 - 1)) == 0) fill_ring(t + 2);
     rs_b = ring[(t + 2 - k) & (kRing - 1)];
     if constexpr (DIR) {
@@ -661,37 +663,41 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             const int u = d0_ + i - 1;
             const int kk = u / R;
             const int rr = u - kk * R;
-            const int ts = j + kk - 1;
-            if (kk != win_k || ts > win_top || ts <= win_top - WW) {
-              // steps ts, ts-1, ... of lane kk in one burst of independent
-              // loads (clamped at step kk, the lane's first real column),
-              // then into the walker's LDS window
-              win_k = kk;
-              win_top = ts;
-              const int base = g * P + kk;
-              if constexpr (NW == 4) {
-                u32x4 tmp[WW];
+            // in a deletion the extend bit of (i, j) was stored with column
+            // j - 1; at j = 1 the deletion can only be opened (D(i,0) = -inf)
+            const int ts = j + kk - 1 - (state == 1 ? 1 : 0);
+            uint32_t w01 = 0, w23 = 0;
+            if (state != 1 || j > 1) {
+              if (kk != win_k || ts > win_top || ts <= win_top - WW) {
+                // steps ts, ts-1, ... of lane kk in one burst of independent
+                // loads (clamped at step kk, the lane's first real column),
+                // then into the walker's LDS window
+                win_k = kk;
+                win_top = ts;
+                const int base = g * P + kk;
+                if constexpr (NW == 4) {
+                  u32x4 tmp[WW];
 #pragma unroll
-                for (int x = 0; x < WW; ++x) tmp[x] = dir4[(ts - x >= kk ? ts - x : kk) * 64 + base];
+                  for (int x = 0; x < WW; ++x) tmp[x] = dir4[(ts - x >= kk ? ts - x : kk) * 64 + base];
 #pragma unroll
-                for (int x = 0; x < WW; ++x) *(u32x4*)(win + 4 * x) = tmp[x];
-              } else {
-                u32x2 tmp[WW];
+                  for (int x = 0; x < WW; ++x) *(u32x4*)(win + 4 * x) = tmp[x];
+                } else {
+                  u32x2 tmp[WW];
 #pragma unroll
-                for (int x = 0; x < WW; ++x) tmp[x] = dir2[(ts - x >= kk ? ts - x : kk) * 64 + base];
+                  for (int x = 0; x < WW; ++x) tmp[x] = dir2[(ts - x >= kk ? ts - x : kk) * 64 + base];
 #pragma unroll
-                for (int x = 0; x < WW; ++x) *(u32x2*)(win + 2 * x) = tmp[x];
+                  for (int x = 0; x < WW; ++x) *(u32x2*)(win + 2 * x) = tmp[x];
+                }
               }
-            }
-            uint32_t w01, w23;
-            if constexpr (NW == 4) {
-              const u32x4 w = *(const u32x4*)(win + 4 * (win_top - ts));
-              w01 = rr >= 8 ? w.z : w.x;
-              w23 = rr >= 8 ? w.w : w.y;
-            } else {
-              const u32x2 w = *(const u32x2*)(win + 2 * (win_top - ts));
-              w01 = w.x;
-              w23 = w.y;
+              if constexpr (NW == 4) {
+                const u32x4 w = *(const u32x4*)(win + 4 * (win_top - ts));
+                w01 = rr >= 8 ? w.z : w.x;
+                w23 = rr >= 8 ? w.w : w.y;
+              } else {
+                const u32x2 w = *(const u32x2*)(win + 2 * (win_top - ts));
+                w01 = w.x;
+                w23 = w.y;
+              }
             }
             const int bit = 8 * h + (rr & 7);  // kinds 0 and 2 at bit, 1 and 3 at bit + 16
             if (state == 0) {
@@ -845,7 +851,13 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, DIR)) void 
   const uint32_t cnt = G(prm->bcount)[bucket];
   const uint32_t items = (cnt + ppi - 1) / ppi;
   const uint32_t* base = prm->sorted + G(prm->bstart)[bucket];
-  for (uint32_t it = (uint32_t)slot_id; it < items; it += (uint32_t)prm->n_slots) {
+  // waves take the bucket's items from a queue head (items differ in cost:
+  // window lengths and traceback paths vary)
+  for (;;) {
+    uint32_t v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(&prm->bhead[bucket], 1u);
+    const uint32_t it = wave_uniform(v);
+    if (it >= items) break;
     const uint32_t first = it * ppi;
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
     run_one<DIR, CLS, KIND, MODE>(prm, base + first, np, lds, slot);

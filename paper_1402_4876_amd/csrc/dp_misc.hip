@@ -14,7 +14,8 @@ __global__ __launch_bounds__(256) void k_rerun(const Params* __restrict__ prm) {
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
   const uint32_t cnt = prm->counters[kCtrRerun];
-  for (uint32_t it = (uint32_t)slot_id; it < cnt; it += (uint32_t)prm->n_slots) {
+  const uint32_t n_waves = gridDim.x * (uint32_t)kWavesPerBlock;
+  for (uint32_t it = (uint32_t)slot_id; it < cnt; it += n_waves) {
     const uint32_t* pp = prm->rerun + it;
     const int p = (int)*pp;
     const int md = prm->mode ? prm->mode[p] : prm->default_mode;
@@ -32,6 +33,7 @@ __global__ void k_zero(const Params* __restrict__ prm) {
   if (i < kNumBuckets) {
     prm->bcount[i] = 0;
     prm->bfill[i] = 0;
+    prm->bhead[i] = 0;
   }
   if (i < kNumCounters) prm->counters[i] = 0;
 }

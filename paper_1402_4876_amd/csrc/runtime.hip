@@ -32,7 +32,8 @@ uint32_t* small_bfill(mica_ctx* c) { return c->d_small + 2 * kNumBuckets; }
 uint32_t* small_qstart(mica_ctx* c) { return c->d_small + 3 * kNumBuckets; }         // +1 entry
 uint32_t* small_qorder(mica_ctx* c) { return c->d_small + 4 * kNumBuckets + 8; }
 uint32_t* small_counters(mica_ctx* c) { return c->d_small + 5 * kNumBuckets + 8; }
-constexpr size_t kSmallWords = 5 * kNumBuckets + 8 + kNumCounters;
+uint32_t* small_bhead(mica_ctx* c) { return c->d_small + 5 * kNumBuckets + 8 + kNumCounters; }
+constexpr size_t kSmallWords = 6 * kNumBuckets + 8 + kNumCounters;
 
 // cost of one work item of a bucket, for the descending work-queue order
 double bucket_cost(int b) {
@@ -229,16 +230,6 @@ mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t
     const size_t colon = c->arch.find(':');
     if (colon != std::string::npos) c->arch.resize(colon);
   }
-  const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
-  for (int d = 0; d < 2; ++d) {
-    int nb = 0;
-    int best = 1;
-    for (int m = 0; m < 2; ++m) {
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kernels().persistent[d][m], 256, shmem));
-      best = std::max(best, nb);
-    }
-    c->occ_blocks[d] = best;
-  }
   HIP_TRY(hipMalloc(&c->d_params, sizeof(Params) * kParamRing));
   HIP_TRY(hipMalloc(&c->d_small, kSmallWords * sizeof(uint32_t)));
   HIP_TRY(hipMalloc(&c->d_class, kMaxM + 1));
@@ -339,14 +330,60 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   mica_status_t st = ensure_pairs(c, b->n_pairs);
   if (st != MICA_OK) return st;
 
-  // scratch: direction bits of a wave (steps x 64 lanes x 16 B) + CIGAR staging
+  // fill launches of this batch
+  const KernelTable& K = kernels();
   const int max_m = b->max_read_len, max_n = b->max_win_len;
-  const size_t dir_bytes = want_start ? (size_t)(max_n + 64) * 64 * 16 : 0;
+  const int d = (want_cigar || (flags & MICA_OUT_START)) ? 1 : 0;
+  const bool forced = flags & MICA_FORCE_INT32;
+  const bool any_local = b->mode ? true : b->default_mode == 1;
+  const bool any_sg = b->mode ? true : b->default_mode == 0;
+  const bool may_sat = !forced && !int16_always_safe(max_m, max_n, *s, any_local, any_sg);
+  const bool plain = flags & MICA_PLAIN_LAUNCH;
+  std::vector<KernelFn> fills;
+  if (!plain && !forced) {
+    if (any_sg) fills.push_back(K.persistent[d][0]);
+    if (any_local) fills.push_back(K.persistent[d][1]);
+  }
+  // plain launches: every bucket in plain mode, else the buckets the
+  // persistent kernel does not serve
+  bool cls_used[kNumClasses] = {};
+  for (int m = 1; m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
+  for (int kind = 0; kind < kNumKinds; ++kind) {
+    if (forced != (kind == kK32)) continue;
+    if (kind == kK16Sat && !may_sat) continue;
+    for (int cls = 0; cls < kNumClasses; ++cls) {
+      if (!cls_used[cls]) continue;
+      for (int md = 0; md < 2; ++md) {
+        if ((md == 1 && !any_local) || (md == 0 && !any_sg)) continue;
+        const int bk = bucket_id(kind, cls, md);
+        if (!plain && persistent_bucket(bk)) continue;
+        fills.push_back(K.bucket[d][bk]);
+      }
+    }
+  }
+  if (may_sat) fills.push_back(K.rerun[d]);
+
+  // scratch: direction bits of a resident wave (steps x 64 lanes x 16 B) +
+  // CIGAR staging, for as many waves as the most occupant fill kernel keeps
+  // resident
+  const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
+  std::vector<int> occ(fills.size());
+  int occ_max = 1;
+  for (size_t i = 0; i < fills.size(); ++i) {
+    auto it = c->occ_cache.find((const void*)fills[i]);
+    if (it == c->occ_cache.end()) {
+      int nb = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fills[i], 256, shmem));
+      it = c->occ_cache.emplace((const void*)fills[i], std::max(nb, 1)).first;
+    }
+    occ[i] = it->second;
+    occ_max = std::max(occ_max, occ[i]);
+  }
+  const size_t dir_bytes = d ? (size_t)(max_n + 64) * 64 * 16 : 0;
   const int stage_stride = max_m + max_n + 2;
-  const size_t stage_bytes = want_start ? (size_t)8 * stage_stride * 4 : 0;
+  const size_t stage_bytes = d ? (size_t)8 * stage_stride * 4 : 0;
   const size_t slot_bytes = std::max<size_t>(align_up(dir_bytes + stage_bytes, 256), 256);
-  const int d = want_start ? 1 : 0;
-  int64_t slots = (int64_t)c->occ_blocks[d] * c->n_cu * kWavesPerBlock;
+  int64_t slots = (int64_t)occ_max * c->n_cu * kWavesPerBlock;
   const int64_t by_ws = (int64_t)(c->ws_cap / slot_bytes);
   slots = std::min(slots, by_ws);
   const int64_t need = (b->n_pairs + 1) / 2 + 3;  // upper bound of work items
@@ -402,6 +439,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.qorder = small_qorder(c);
   P.class_of_m = c->d_class;
   P.counters = small_counters(c);
+  P.bhead = small_bhead(c);
   P.scratch = c->d_scratch;
   P.slot_bytes = slot_bytes;
   P.dir_bytes = dir_bytes;
@@ -413,43 +451,18 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   HIP_TRY(hipEventRecord(c->ev[rp], stream));
   c->ev_used[rp] = true;
 
-  const KernelTable& K = kernels();
   const unsigned pblocks = (unsigned)((b->n_pairs + 255) / 256);
-  const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
-  const unsigned fblocks = (unsigned)(slots / kWavesPerBlock);
   std::vector<Launch> seq;
   seq.push_back({K.zero, 1, 256, 0, false});
   seq.push_back({K.plan, pblocks, 256, 0, false});
   seq.push_back({K.scan, 1, 64, 0, false});
   seq.push_back({K.scatter, pblocks, 256, 0, false});
-
-  const bool forced = flags & MICA_FORCE_INT32;
-  const bool any_local = b->mode ? true : b->default_mode == 1;
-  const bool any_sg = b->mode ? true : b->default_mode == 0;
-  const bool may_sat = !forced && !int16_always_safe(max_m, max_n, *s, any_local, any_sg);
-  const bool plain = flags & MICA_PLAIN_LAUNCH;
-  if (!plain && !forced) {
-    if (any_sg) seq.push_back({K.persistent[d][0], fblocks, 256, shmem, true});
-    if (any_local) seq.push_back({K.persistent[d][1], fblocks, 256, shmem, true});
+  for (size_t i = 0; i < fills.size(); ++i) {
+    // each fill kernel gets the blocks it keeps resident (its waves index
+    // the first slots of the scratch)
+    const int64_t blocks = std::min<int64_t>((int64_t)occ[i] * c->n_cu, slots / kWavesPerBlock);
+    seq.push_back({fills[i], (unsigned)std::max<int64_t>(blocks, 1), 256, shmem, true});
   }
-  // plain launches: every bucket in plain mode, else the buckets the
-  // persistent kernel does not serve
-  bool cls_used[kNumClasses] = {};
-  for (int m = 1; m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
-  for (int kind = 0; kind < kNumKinds; ++kind) {
-    if (forced != (kind == kK32)) continue;
-    if (kind == kK16Sat && !may_sat) continue;
-    for (int cls = 0; cls < kNumClasses; ++cls) {
-      if (!cls_used[cls]) continue;
-      for (int md = 0; md < 2; ++md) {
-        if ((md == 1 && !any_local) || (md == 0 && !any_sg)) continue;
-        const int bk = bucket_id(kind, cls, md);
-        if (!plain && persistent_bucket(bk)) continue;
-        seq.push_back({K.bucket[d][bk], fblocks, 256, shmem, true});
-      }
-    }
-  }
-  if (may_sat) seq.push_back({K.rerun[d], fblocks, 256, shmem, true});
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (c->timing) {
     HIP_TRY(take_event(c, &t0));

@@ -11,11 +11,18 @@ def run_gpu(ctx, batch, scoring=(1, -4, 6, 1), trace=True, cap=64, force_int32=F
     import paper_1402_4876_amd as mica
     dev = mica.to_device(batch)
     md = dev["mode"] if mode == "batch" else None
+    # every output starts as a sentinel, so a pair the kernels skip cannot
+    # pass on values left in reused device memory
+    n = batch.n_pairs
+    keys = ["score", "read_end", "ref_end", "status"] + (["read_start", "ref_start", "n_cigar"] if trace else [])
+    sentinel = {k: torch.full((n,), -7, dtype=torch.int32, device="cuda") for k in keys}
+    if trace:
+        sentinel["cigar"] = torch.full((n, cap), -7, dtype=torch.int32, device="cuda")
     out = mica.align(ctx, dev["ref2b"], dev["win_off"], dev["win_len"], dev["reads2b"], dev["read_off"],
                      dev["read_len"], mode=md, scoring=scoring, out_cigar=trace, cigar_cap=cap,
                      force_int32=force_int32, plain=plain, ref_len=dev["ref_len"], reads_len=dev["reads_len"],
                      max_read_len=max_read_len, max_win_len=max_win_len,
-                     default_mode=int(batch.mode[0]) if mode != "batch" and batch.n_pairs else 0)
+                     default_mode=int(batch.mode[0]) if mode != "batch" and batch.n_pairs else 0, out=sentinel)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
 

@@ -224,11 +224,13 @@ def test_pack_2bit_on_gpu(ctx):
     assert np.array_equal(w.cpu().numpy().view(np.uint32), mica.pack_codes(codes))
 
 
-def test_config1_full_size_sampled(ctx):
-    """The benchmark's batch (10^6 pairs, persistent launch): sampled pairs against the
-    oracle, every pair against properties that hold at any size."""
+@pytest.mark.parametrize("plain", [False, True])
+def test_config1_full_size_sampled(ctx, plain):
+    """The benchmark's batch (10^6 pairs, far more work items than resident waves),
+    through both launch styles: sampled pairs against the oracle, every pair against
+    properties that hold at any size."""
     b = synth.config1()
-    g = U.run_gpu(ctx, b, SC, max_read_len=150, max_win_len=400)
+    g = U.run_gpu(ctx, b, SC, max_read_len=150, max_win_len=400, plain=plain)
     idx = np.sort(np.random.default_rng(8).choice(b.n_pairs, 3000, replace=False))
     U.assert_same(g, U.run_oracle(b, SC, idx=idx), idx=idx, what="c1 sample")
     assert not g["status"].any()
