@@ -54,7 +54,7 @@ struct mica_ctx {
   int ring_pos = 0;
   uint8_t class_of_m[mica::kMaxM + 1];
   uint32_t qorder[mica::kNumBuckets];
-  uint32_t persist_q[3] = {0, 0, 0};
+  uint32_t persist_q[mica::kQueueParts] = {};
   bool class_dirty = true;
   // fill-kernel timing
   bool timing = false;

@@ -40,27 +40,34 @@ __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
   return (kind == kK32 ? 1 : 2) * (64 / class_lanes(cls));
 }
 
-// The persistent kernel serves the packed 16-bit buckets of the 16-lane
-// classes (the bulk of short-read work); the other buckets run as plain
-// per-bucket launches after it.
-// Classes above kPersistMaxClass (reads over 224 bases) need more registers
-// than the persistent kernels' budget and run as plain launches instead.
+// The persistent kernels serve the packed 16-bit buckets of the 16-lane
+// classes (the bulk of short-read work), split in two class ranges per mode
+// so that the short classes run with more resident waves: part 0 holds
+// classes 0..kPersistSmallMax, part 1 the classes up to kPersistMaxClass.
+// The other buckets run as plain per-bucket launches after them.
 #ifndef MICA_PERSIST_MAX_CLASS
 #define MICA_PERSIST_MAX_CLASS 13
 #endif
+constexpr int kPersistSmallMax = 9;
 constexpr int kPersistMaxClass = MICA_PERSIST_MAX_CLASS;
 __host__ __device__ constexpr bool persistent_bucket(int b) {
   return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16 && bucket_class(b) <= kPersistMaxClass;
 }
-// the ordering key of buckets in the work queue: persistent semi-global, then
-// persistent local, then the rest
-__host__ __device__ constexpr int queue_part(int b) { return persistent_bucket(b) ? bucket_mode(b) : 2; }
+__host__ __device__ constexpr int persist_part(int cls) { return cls <= kPersistSmallMax ? 0 : 1; }
+// queue part of a persistent (mode, part): the long-read part of a mode
+// first (its items cost most), then the short-read part
+__host__ __device__ constexpr int persist_queue_part(int mode, int part) { return mode * 2 + (part ? 0 : 1); }
+constexpr int kQueueParts = 5;  // four persistent parts, then everything else
+// the ordering key of buckets in the work queue
+__host__ __device__ constexpr int queue_part(int b) {
+  return persistent_bucket(b) ? persist_queue_part(bucket_mode(b), persist_part(bucket_class(b))) : 4;
+}
 
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
 // counters[] slots
-// (queue heads of the two persistent kernels: kCtrQueueHead + mode)
-enum : int { kCtrQueueHead = 0, kCtrRerun = 2, kCtrItems = 3, kCtrRerunHead = 4, kNumCounters = 8 };
+// (queue heads of the four persistent kernels: kCtrQueueHead + queue part)
+enum : int { kCtrQueueHead = 0, kCtrRerun = 4, kCtrItems = 5, kCtrRerunHead = 6, kNumCounters = 8 };
 
 // per-pair status bits (same values as the public header)
 constexpr uint32_t kStSaturated = 1u << 0;
@@ -124,7 +131,7 @@ struct Params {
   uint64_t dir_bytes;          // direction-bit part of a slot
   int32_t stage_stride;        // CIGAR staging words per pair
   int32_t n_slots;             // resident waves the scratch is sized for
-  uint32_t persist_q[3];       // queue positions [persist_q[m], persist_q[m+1]) of mode m's persistent kernel
+  uint32_t persist_q[kQueueParts];  // queue positions [persist_q[q], persist_q[q+1]) of queue part q
 };
 
 }  // namespace mica
@@ -134,7 +141,7 @@ typedef void (*KernelFn)(const Params*);
 // Kernel entry points of the library, indexed for the host runtime.
 struct KernelTable {
   KernelFn bucket[2][kNumBuckets];  // [with traceback][bucket]
-  KernelFn persistent[2][2];  // [with traceback][mode]
+  KernelFn persistent[2][2][2];  // [with traceback][mode][class part]
   KernelFn rerun[2];
   KernelFn zero, plan, scan, scatter;
   KernelTable();

@@ -188,13 +188,11 @@ __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool d
 #ifndef MICA_ROW_SCHED_BARRIER
 #define MICA_ROW_SCHED_BARRIER 1
 #endif
-// the persistent kernels hold every 16-lane class of one mode
-#ifndef MICA_PERSIST_WAVES_SG
-#define MICA_PERSIST_WAVES_SG 3
-#endif
-#ifndef MICA_PERSIST_WAVES_LOCAL
-#define MICA_PERSIST_WAVES_LOCAL 2
-#endif
+// Resident waves per SIMD of a persistent kernel (all classes of its part
+// share one register budget)
+__host__ __device__ constexpr int persist_waves(bool dir, int mode, int part) {
+  return mode == 0 ? (part == 0 && dir ? 4 : 3) : (part == 0 ? 3 : 2);
+}
 
 // Lanes of one wave exchange values through LDS: LDS operations of a wave
 // complete in order, and the wave-scope fences keep the compiler from moving
@@ -788,23 +786,26 @@ __device__ __forceinline__ void run_one(const Params* prm, const uint32_t* pairs
     process_item<V16, P, R, MODE, DIR, KIND == kK16Sat>(prm, pairs, np, lds, slot);
 }
 
-template <bool DIR, int MODE, int CLS = 0>
+template <bool DIR, int MODE, int CLS, int CHI>
 __device__ __forceinline__ void dispatch(int bucket, const Params* prm, const uint32_t* pairs, int np,
                                          uint32_t* lds, uint8_t* slot) {
-  if constexpr (CLS <= kPersistMaxClass) {
+  if constexpr (CLS <= CHI) {
     if (bucket_class(bucket) == CLS) run_one<DIR, CLS, kK16, MODE>(prm, pairs, np, lds, slot);
-    else dispatch<DIR, MODE, CLS + 1>(bucket, prm, pairs, np, lds, slot);
+    else dispatch<DIR, MODE, CLS + 1, CHI>(bucket, prm, pairs, np, lds, slot);
   }
 }
 
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Persistent launch (one per mode): every resident wave takes work items from
-// the mode's part of the queue (buckets in descending cost order) until it is
-// empty.
-template <bool DIR, int MODE>
-__global__ __launch_bounds__(256, MODE ? MICA_PERSIST_WAVES_LOCAL : MICA_PERSIST_WAVES_SG) void
+// Persistent launch (one per mode and class part): every resident wave takes
+// work items from its part of the queue (buckets in descending cost order)
+// until it is empty.
+template <bool DIR, int MODE, int PART>
+__global__ __launch_bounds__(256, persist_waves(DIR, MODE, PART)) void
 k_fill_persistent(const Params* __restrict__ prm) {
+  constexpr int QP = persist_queue_part(MODE, PART);
+  constexpr int CLO = PART == 0 ? 0 : kPersistSmallMax + 1;
+  constexpr int CHI = PART == 0 ? kPersistSmallMax : kPersistMaxClass;
   extern __shared__ uint32_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -812,12 +813,12 @@ k_fill_persistent(const Params* __restrict__ prm) {
   if (slot_id >= prm->n_slots) return;
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
-  const int q0 = (int)prm->persist_q[MODE], q1 = (int)prm->persist_q[MODE + 1];
+  const int q0 = (int)prm->persist_q[QP], q1 = (int)prm->persist_q[QP + 1];
   const uint32_t base_item = G(prm->qstart)[q0];
   const uint32_t total = G(prm->qstart)[q1];
   for (;;) {
     uint32_t v = 0;
-    if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead + MODE], 1u);
+    if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead + QP], 1u);
     const uint32_t item = base_item + wave_uniform(v);
     if (item >= total) break;
     // queue position: last q with qstart[q] <= item
@@ -833,7 +834,7 @@ k_fill_persistent(const Params* __restrict__ prm) {
     const uint32_t first = idx * (uint32_t)ppi;
     const uint32_t cnt = G(prm->bcount)[bucket];
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    dispatch<DIR, MODE>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
+    dispatch<DIR, MODE, CLO, CHI>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
   }
 }
 

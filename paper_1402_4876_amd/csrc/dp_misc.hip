@@ -115,8 +115,7 @@ __global__ void k_scan(const Params* __restrict__ prm) {
   }
   prm->qstart[kNumBuckets] = items;
   prm->counters[kCtrItems] = items;
-  prm->counters[kCtrQueueHead] = 0;
-  prm->counters[kCtrQueueHead + 1] = 0;
+  for (int q = 0; q < 4; ++q) prm->counters[kCtrQueueHead + q] = 0;
   prm->counters[kCtrRerun] = 0;
 }
 
@@ -163,18 +162,15 @@ namespace mica {
   X(k16s, 0, 0) X(k16s, 0, 1) X(k16s, 1, 0) X(k16s, 1, 1) \
   X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1)
 MICA_FILL_ALL(MICA_FILL_DECL)
-void reg_persistent_0_0(KernelTable& t);
-void reg_persistent_0_1(KernelTable& t);
-void reg_persistent_1_0(KernelTable& t);
-void reg_persistent_1_1(KernelTable& t);
+#define MICA_PERSIST_ALL(X) X(0, 0, 0) X(0, 0, 1) X(0, 1, 0) X(0, 1, 1) X(1, 0, 0) X(1, 0, 1) X(1, 1, 0) X(1, 1, 1)
+#define MICA_PERSIST_DECL(dir, mode, part) void reg_persistent_##dir##_##mode##_##part(KernelTable& t);
+MICA_PERSIST_ALL(MICA_PERSIST_DECL)
 
 KernelTable::KernelTable() {
 #define MICA_FILL_CALL(kind, mode, dir) reg_fill_##kind##_##mode##_##dir(*this);
   MICA_FILL_ALL(MICA_FILL_CALL)
-  reg_persistent_0_0(*this);
-  reg_persistent_0_1(*this);
-  reg_persistent_1_0(*this);
-  reg_persistent_1_1(*this);
+#define MICA_PERSIST_CALL(dir, mode, part) reg_persistent_##dir##_##mode##_##part(*this);
+  MICA_PERSIST_ALL(MICA_PERSIST_CALL)
   rerun[0] = &k_rerun<false>;
   rerun[1] = &k_rerun<true>;
   zero = &k_zero;

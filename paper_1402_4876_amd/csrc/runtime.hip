@@ -245,10 +245,8 @@ mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t
     if (queue_part(x) != queue_part(y)) return queue_part(x) < queue_part(y);
     return bucket_cost(x) > bucket_cost(y);
   });
-  for (int b = 0; b < kNumBuckets; ++b) {
-    if (queue_part(b) == 0) c->persist_q[1]++;
-    if (queue_part(b) <= 1) c->persist_q[2]++;
-  }
+  for (int b = 0; b < kNumBuckets; ++b)
+    for (int q = queue_part(b); q + 1 < kQueueParts; ++q) c->persist_q[q + 1]++;
   for (int q = 0; q < kNumBuckets; ++q) c->qorder[q] = (uint32_t)order[q];
   HIP_TRY(hipMemcpy(small_qorder(c), c->qorder, sizeof(c->qorder), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_class, c->class_of_m, kMaxM + 1, hipMemcpyHostToDevice));
@@ -339,15 +337,22 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   const bool any_sg = b->mode ? true : b->default_mode == 0;
   const bool may_sat = !forced && !int16_always_safe(max_m, max_n, *s, any_local, any_sg);
   const bool plain = flags & MICA_PLAIN_LAUNCH;
-  std::vector<KernelFn> fills;
-  if (!plain && !forced) {
-    if (any_sg) fills.push_back(K.persistent[d][0]);
-    if (any_local) fills.push_back(K.persistent[d][1]);
-  }
-  // plain launches: every bucket in plain mode, else the buckets the
-  // persistent kernel does not serve
   bool cls_used[kNumClasses] = {};
   for (int m = 1; m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
+  std::vector<KernelFn> fills;
+  if (!plain && !forced) {
+    // persistent parts in queue order: per mode, long reads first
+    bool part_used[2] = {false, false};
+    for (int cls = 0; cls <= kPersistMaxClass; ++cls)
+      if (cls_used[cls] && class_lanes(cls) == 16) part_used[persist_part(cls)] = true;
+    for (int md = 0; md < 2; ++md) {
+      if ((md == 0 && !any_sg) || (md == 1 && !any_local)) continue;
+      for (int part : {1, 0})
+        if (part_used[part]) fills.push_back(K.persistent[d][md][part]);
+    }
+  }
+  // plain launches: every bucket in plain mode, else the buckets the
+  // persistent kernels do not serve
   for (int kind = 0; kind < kNumKinds; ++kind) {
     if (forced != (kind == kK32)) continue;
     if (kind == kK16Sat && !may_sat) continue;
@@ -445,7 +450,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.dir_bytes = dir_bytes;
   P.stage_stride = stage_stride;
   P.n_slots = (int32_t)slots;
-  for (int i = 0; i < 3; ++i) P.persist_q[i] = c->persist_q[i];
+  for (int i = 0; i < kQueueParts; ++i) P.persist_q[i] = c->persist_q[i];
   Params* dp = c->d_params + rp;
   HIP_TRY(hipMemcpyAsync(dp, &P, sizeof(Params), hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(c->ev[rp], stream));
