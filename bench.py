@@ -41,8 +41,8 @@ OPS_PER_CELL = {("sg", True): 13, ("sg", False): 9, ("local", True): 16, ("local
 KERNEL_SOURCES = ("dp_fill.h", "dp_common.h")
 MEASURED_TRAFFIC = {
     # config: (kernel source sha256, fetch bytes, write bytes)
-    "c1": ("d4a59a266002a7892cdaa6690b9df4b8b374a329dcc1787345bafe0a6e113f4c",
-           round(1.15609e7 * 2048), round(5.21404e7 * 1024)),
+    "c1": ("634bd6d4747fe648733de9f72fca0077e49b4b185e9105925690e8de17c0012f",
+           round(1.19941e7 * 2048), round(5.23492e7 * 1024)),
 }
 
 
