@@ -122,7 +122,7 @@ def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
     return base, parity
 
 
-def serving_bench(n_per_rate=2000, warmup=200, pool_size=32, slots=4, fracs=(0.3, 0.6, 0.9)):
+def serving_bench(n_per_rate=2000, warmup=200, pool_size=32, slots=4, fracs=(0.3, 0.6, 0.9), fifo_baseline=True):
     """Open-loop serving of config-4 requests: a 3 Gbp reference resident on the
     GPU, requests of 1..10,000 reads of {100, 150, 250} bp (windows 1.5 m + 64,
     semi-global, full outputs) arriving as a Poisson stream at 0.3 / 0.6 / 0.9
@@ -146,10 +146,16 @@ def serving_bench(n_per_rate=2000, warmup=200, pool_size=32, slots=4, fracs=(0.3
         w, ro, rl, wo, wl, _ = pool[rid % pool_size]
         srv.submit(rid, w, ro, rl, wo, wl, arrival=arrival)
 
+    max_n = max(len(p[2]) for p in pool)
+    fetch_buf = {k: np.empty(max_n, np.int32) for k in ("score", "read_start", "read_end", "ref_start",
+                                                         "ref_end", "n_cigar", "status")}
+    fetch_buf["cigar"] = np.empty((max_n, 64), np.uint32)
+
     def drain(srv, pending, until_empty):
+        # every finished request's outputs are fetched (into reused buffers)
         while pending:
             for i in srv.poll():
-                srv.fetch(i)
+                srv.fetch(i, out=fetch_buf)
                 pending.discard(i)
             if not until_empty:
                 return
@@ -202,6 +208,8 @@ def serving_bench(n_per_rate=2000, warmup=200, pool_size=32, slots=4, fracs=(0.3
             log("serving batching %.1f x max: %s" % (f, r))
     finally:
         srv.close()
+    if not fifo_baseline:
+        return out
     fifo = mica.Server(ref, ref_len, slots=1, fifo=True)
     try:
         out["fifo_baseline"] = {"slots": 1, "rates": []}
@@ -240,11 +248,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (request stream) measurement")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
+    ap.add_argument("--serve-slots", type=int, default=4, help="in-flight slots of the serving measurement")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (no batch step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.serve_only:
+        res = serving_bench(n_per_rate=args.serve_requests, warmup=max(args.serve_requests // 10, 20),
+                            slots=args.serve_slots, fifo_baseline=False)
+        print(json.dumps({"serving": res}), flush=True)
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(pairs are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
@@ -329,7 +344,8 @@ def main():
         "resident_waves": int(stats["n_waves"]),
     }
     if not args.no_serving:
-        res["serving"] = serving_bench(n_per_rate=args.serve_requests, warmup=max(args.serve_requests // 10, 20))
+        res["serving"] = serving_bench(n_per_rate=args.serve_requests, warmup=max(args.serve_requests // 10, 20),
+                                       slots=args.serve_slots)
     if not args.no_cpu_baseline:
         base, parity = cpu_baseline(batch, host, want_trace)
         res["cpu_baseline"] = base

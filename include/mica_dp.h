@@ -217,11 +217,11 @@ mica_status_t mica_ctx_read_timing(mica_ctx_t ctx, double *fill_ms, int64_t *n_b
 /* ---- Serving ------------------------------------------------------------
  * A server keeps the reference resident on one GPU and aligns requests of
  * reads submitted from the host (the paper's host controller that feeds the
- * card large batches and keeps it busy, architecture section).  A worker
- * thread packs every queued request that fits (oldest first; up to 65,536
- * reads per batch) into the next free in-flight slot; each slot has its own
- * HIP stream, library context and staging, so copies and kernels of
- * different slots overlap (continuous batching).  Requests whose staging
+ * card large batches and keeps it busy, architecture section).  Each of the
+ * in-flight slots has a host thread that takes every queued request that
+ * fits (oldest first; up to 65,536 reads per batch) into its staging; each
+ * slot has its own HIP stream, library context and staging, so host work,
+ * copies and kernels of different slots overlap (continuous batching).  Requests whose staging
  * would not fit wait in the queue (admission by the slots' HBM budget).
  * Results are exact and identical to mica_dp_align_batch on the same pairs,
  * whatever else shares the batch.  All server calls are thread-safe. */
@@ -258,8 +258,9 @@ mica_status_t mica_server_submit(mica_server_t server, uint64_t request_id, cons
 mica_status_t mica_server_poll(mica_server_t server, uint64_t *done_ids, int64_t cap, int64_t *n_done);
 
 /* Copy a finished request's outputs (n entries each, as mica_dp_align_batch;
- * cigar: n * cigar_cap words, at most 64 runs kept; any pointer may be NULL)
- * and forget the request.  MICA_ERR_BUSY while it is not finished. */
+ * cigar: rows of cigar_cap words, of which the first min(|n_cigar|, 64,
+ * cigar_cap) are written; any pointer may be NULL) and forget the request.
+ * MICA_ERR_BUSY while it is not finished. */
 mica_status_t mica_server_fetch(mica_server_t server, uint64_t request_id, int32_t *score,
                                 int32_t *read_start, int32_t *read_end, int32_t *ref_start, int32_t *ref_end,
                                 uint32_t *cigar, int32_t cigar_cap, int32_t *n_cigar, uint32_t *status);

@@ -5,9 +5,10 @@
 //
 // This is the host side of the paper's controller design (architecture
 // section: the host hands large batches to the card and keeps it busy while it
-// waits on I/O), restated for one GPU: requests queue FIFO, a worker thread
-// packs every queued request that fits into the next free slot, and the
-// slots' copies and kernels overlap on their own streams.
+// waits on I/O), restated for one GPU: requests queue FIFO; each slot has a
+// host thread that packs every queued request that fits into its staging,
+// launches it on the slot's stream and hands the outputs back, so the slots'
+// host work, copies and kernels all overlap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,8 +52,9 @@ struct Request {
   std::vector<uint64_t> read_off, win_off;
   std::vector<int32_t> read_len, win_len;
   std::vector<uint8_t> mode;
-  std::vector<int32_t> out;     // 7 * n: score, read_end, ref_end, read_start, ref_start, n_cigar, status
-  std::vector<uint32_t> cigar;  // n * cigar_cap
+  std::vector<int32_t> out;       // 7 * n: score, read_end, ref_end, read_start, ref_start, n_cigar, status
+  std::vector<uint32_t> cigar;    // the runs each read has, back to back
+  std::vector<uint32_t> cig_off;  // n + 1 offsets into cigar
 };
 
 struct Slot {
@@ -116,7 +118,7 @@ struct mica_server {
   double first_arrival = -1, last_done = 0;
   std::string error;
   bool stop = false;
-  std::thread worker;
+  std::vector<std::thread> workers;  // one per slot
 };
 
 namespace {
@@ -126,29 +128,55 @@ void set_error(mica_server* s, const std::string& e) {
   if (s->error.empty()) s->error = e;
 }
 
-// complete the requests of a finished slot (called with the lock held)
-void finish_slot(mica_server* s, Slot& sl, bool failed) {
+// copy a finished slot's outputs into its requests (the slot's thread owns
+// them; no lock held)
+void fill_outputs(mica_server* s, Slot& sl, bool failed) {
   const int64_t n = sl.n_pairs;
   const int cap = s->cigar_cap;
   const int32_t* o = (const int32_t*)sl.h_out;
   const uint32_t* cg = (const uint32_t*)(sl.h_out + align_up((size_t)7 * kSlotPairs * 4, 256));
   int64_t base = 0;
-  const double t = now_s(s->t0);
   for (auto& r : sl.reqs) {
     r->out.assign((size_t)7 * r->n, 0);
     for (int k = 0; k < 7; ++k)
       std::memcpy(r->out.data() + (size_t)k * r->n, o + (size_t)k * n + base, (size_t)r->n * 4);
     if (failed)
-      for (int64_t p = 0; p < r->n; ++p) r->out[(size_t)6 * r->n + p] = (int32_t)MICA_ST_INTERNAL;
-    if (cap > 0) r->cigar.assign(cg + (size_t)base * cap, cg + (size_t)(base + r->n) * cap);
+      for (int64_t p = 0; p < r->n; ++p) {
+        r->out[(size_t)5 * r->n + p] = 0;
+        r->out[(size_t)6 * r->n + p] = (int32_t)MICA_ST_INTERNAL;
+      }
+    if (cap > 0) {
+      // keep only the runs each read has (n_cigar, at most cap), not the
+      // whole cap-wide rows
+      const int32_t* nc = r->out.data() + (size_t)5 * r->n;
+      r->cig_off.resize((size_t)r->n + 1);
+      size_t tot = 0;
+      for (int64_t p = 0; p < r->n; ++p) {
+        r->cig_off[(size_t)p] = (uint32_t)tot;
+        const int32_t k = nc[p] < 0 ? -nc[p] : nc[p];
+        tot += (size_t)std::max(0, std::min(k, cap));
+      }
+      r->cig_off[(size_t)r->n] = (uint32_t)tot;
+      r->cigar.resize(tot);
+      for (int64_t p = 0; p < r->n; ++p)
+        std::memcpy(r->cigar.data() + r->cig_off[(size_t)p], cg + (size_t)(base + p) * cap,
+                    (size_t)(r->cig_off[(size_t)p + 1] - r->cig_off[(size_t)p]) * 4);
+    }
+    base += r->n;
+  }
+}
+
+// mark a slot's requests finished (lock held)
+void complete_slot(mica_server* s, Slot& sl) {
+  const double t = now_s(s->t0);
+  for (auto& r : sl.reqs) {
     r->done = t;
     r->finished = true;
     s->latencies.push_back(r->done - r->arrival);
     s->cells_done += r->cells;
-    s->last_done = std::max(s->last_done, t);
     s->done_ids.push_back(r->id);
-    base += r->n;
   }
+  s->last_done = std::max(s->last_done, t);
   sl.reqs.clear();
   sl.busy = false;
   sl.n_pairs = 0;
@@ -237,54 +265,45 @@ bool launch_slot(mica_server* s, Slot& sl) {
   return true;
 }
 
-void worker_main(mica_server* s) {
+// One thread per slot: take every queued request that fits (oldest first),
+// stage and launch it on the slot's stream, wait for its event, hand the
+// outputs back.  The slots' threads run their host work in parallel.
+void slot_main(mica_server* s, Slot* sl) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
-    bool progress = false;
-    // completions
-    for (Slot& sl : s->slots) {
-      if (!sl.busy) continue;
-      const hipError_t q = hipEventQuery(sl.done);
-      if (q == hipErrorNotReady) continue;
-      if (q != hipSuccess && s->error.empty()) s->error = std::string("serving event: ") + hipGetErrorString(q);
-      finish_slot(s, sl, q != hipSuccess);
-      progress = true;
+    if (s->queue.empty()) {
+      if (s->stop) break;
+      s->cv.wait_for(lk, std::chrono::milliseconds(5));
+      continue;
     }
-    // new batches: every queued request that fits, oldest first
-    for (Slot& sl : s->slots) {
-      if (sl.busy || s->queue.empty()) continue;
-      int64_t pairs = 0, words = 0;
-      while (!s->queue.empty()) {
-        const auto& r = s->queue.front();
-        if (pairs + r->n > kSlotPairs || words + (int64_t)r->reads.size() > kSlotWords) break;
-        pairs += r->n;
-        words += (int64_t)r->reads.size();
-        sl.reqs.push_back(r);
-        s->queue.pop_front();
-        if (s->fifo) break;
+    int64_t pairs = 0, words = 0;
+    while (!s->queue.empty()) {
+      const auto& r = s->queue.front();
+      if (pairs + r->n > kSlotPairs || words + (int64_t)r->reads.size() > kSlotWords) break;
+      pairs += r->n;
+      words += (int64_t)r->reads.size();
+      sl->reqs.push_back(r);
+      s->queue.pop_front();
+      if (s->fifo) break;
+    }
+    sl->busy = true;
+    lk.unlock();
+    bool ok = launch_slot(s, *sl);
+    if (ok) {
+      // busy slots are polled every 20 us
+      hipError_t q;
+      while ((q = hipEventQuery(sl->done)) == hipErrorNotReady) std::this_thread::sleep_for(std::chrono::microseconds(20));
+      if (q != hipSuccess) {
+        set_error(s, std::string("serving event: ") + hipGetErrorString(q));
+        ok = false;
       }
-      if (sl.reqs.empty()) continue;
-      sl.busy = true;
-      lk.unlock();
-      const bool ok = launch_slot(s, sl);
-      if (!ok) (void)hipStreamSynchronize(sl.stream);  // let what was enqueued finish before reuse
-      lk.lock();
-      if (!ok) finish_slot(s, sl, true);
-      progress = true;
+    } else {
+      (void)hipStreamSynchronize(sl->stream);  // let what was enqueued finish before reuse
     }
-    if (s->stop) {
-      bool any = false;
-      for (Slot& sl : s->slots) any |= sl.busy;
-      if (!any && s->queue.empty()) break;
-    }
-    if (!progress) {
-      bool any_busy = false;
-      for (Slot& sl : s->slots) any_busy |= sl.busy;
-      // busy slots are polled every 20 us; otherwise sleep until a submit
-      if (any_busy) s->cv.wait_for(lk, std::chrono::microseconds(20));
-      else s->cv.wait_for(lk, std::chrono::milliseconds(5));
-    }
+    fill_outputs(s, *sl, !ok);
+    lk.lock();
+    complete_slot(s, *sl);
   }
 }
 
@@ -369,7 +388,7 @@ mica_status_t mica_server_create(int hip_device, const uint32_t* host_ref2b, uin
     const mica_status_t st = mica_ctx_create(hip_device, ws, &sl.ctx);
     if (st != MICA_OK) return bail(st, std::string("slot context: ") + mica_last_error());
   }
-  s->worker = std::thread(worker_main, s);
+  for (Slot& sl : s->slots) s->workers.emplace_back(slot_main, s, &sl);
   *out = s;
   return MICA_OK;
 }
@@ -461,10 +480,13 @@ mica_status_t mica_server_fetch(mica_server_t s, uint64_t request_id, int32_t* s
   put(ref_start, 4);
   put(n_cigar, 5);
   put((int32_t*)status, 6);
-  if (cigar && cigar_cap > 0 && s->cigar_cap > 0) {
-    const int c = std::min(cigar_cap, s->cigar_cap);
-    for (int64_t p = 0; p < n; ++p)
-      std::memcpy(cigar + (size_t)p * cigar_cap, r->cigar.data() + (size_t)p * s->cigar_cap, (size_t)c * 4);
+  if (cigar && cigar_cap > 0 && s->cigar_cap > 0 && !r->cig_off.empty()) {
+    // the runs of each read (words past them in a row are left as they were)
+    for (int64_t p = 0; p < n; ++p) {
+      const uint32_t a = r->cig_off[(size_t)p];
+      const uint32_t k = std::min<uint32_t>(r->cig_off[(size_t)p + 1] - a, (uint32_t)cigar_cap);
+      std::memcpy(cigar + (size_t)p * cigar_cap, r->cigar.data() + a, (size_t)k * 4);
+    }
   }
   return MICA_OK;
 }
@@ -506,7 +528,8 @@ mica_status_t mica_server_destroy(mica_server_t s) {
     s->stop = true;
   }
   s->cv.notify_all();
-  if (s->worker.joinable()) s->worker.join();
+  for (auto& w : s->workers)
+    if (w.joinable()) w.join();
   (void)hipSetDevice(s->device);
   for (Slot& sl : s->slots)
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);

@@ -63,12 +63,21 @@ class Server:
         _lib.check(_lib.load().mica_server_poll(self._h, ids.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(k)))
         return [int(x) for x in ids[:k.value]]
 
-    def fetch(self, request_id, cigar_cap=64):
+    def fetch(self, request_id, cigar_cap=64, out=None):
+        """Outputs of a finished request as numpy arrays.  ``out`` may hold
+        preallocated arrays (at least n entries each, cigar rows of cigar_cap
+        words) to fill instead of new ones; CIGAR words past a read's runs are
+        left as they were."""
         n = self._n.get(int(request_id), 0)  # unknown ids: the library reports the error
-        out = {k: np.zeros(n, np.int32) for k in ("score", "read_start", "read_end", "ref_start", "ref_end",
-                                                   "n_cigar", "status")}
+        keys = ("score", "read_start", "read_end", "ref_start", "ref_end", "n_cigar", "status")
         cap = cigar_cap if self.out_cigar else 0
-        out["cigar"] = np.zeros((n, max(cap, 1)), np.uint32)
+        if out is None:
+            out = {k: np.empty(n, np.int32) for k in keys}
+            out["cigar"] = np.zeros((n, max(cap, 1)), np.uint32)
+        else:
+            out = {k: out[k][:n] for k in keys + ("cigar",)}
+            if out["cigar"].shape[1] != max(cap, 1):
+                raise ValueError("out['cigar'] rows must have cigar_cap words")
         p = {k: v.ctypes.data_as(ctypes.c_void_p) for k, v in out.items()}
         _lib.check(_lib.load().mica_server_fetch(self._h, int(request_id), p["score"], p["read_start"],
                                                  p["read_end"], p["ref_start"], p["ref_end"], p["cigar"], cap,
