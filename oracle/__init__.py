@@ -31,6 +31,7 @@ ST_READ_OOB = 1 << 4
 
 SEMIGLOBAL = 0
 LOCAL = 1
+EXTEND = 2
 
 DEFAULT_SCORING = (1, -4, 6, 1)  # match, mismatch, gap open, gap extend
 
@@ -46,22 +47,33 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def bind(lib):
+    """Declare the C entry points of a loaded oracle library (also used by tests
+    that load modified builds)."""
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int32
+    lib.oracle_align_batch.restype = ctypes.c_int
+    lib.oracle_align_batch.argtypes = [
+        P, i64, P, P, P, i64, P, P, P, i32, i64,
+        i32, i32, i32, i32, i32, i32,
+        P, P, P, P, P, P, P, P, i32,
+    ]
+    lib.oracle_align_batch_ext.restype = ctypes.c_int
+    lib.oracle_align_batch_ext.argtypes = [
+        P, i64, P, P, P, i64, P, P, P, i32, P, i32, i32, i64,
+        i32, i32, i32, i32, i32, i32,
+        P, P, P, P, P, P, P, P, i32,
+    ]
+    return lib
+
+
 def _load():
     global _lib
     with _lock:
         if _lib is None:
             build()
-            lib = ctypes.CDLL(_LIB)
-            P = ctypes.c_void_p
-            i64 = ctypes.c_int64
-            i32 = ctypes.c_int32
-            lib.oracle_align_batch.restype = ctypes.c_int
-            lib.oracle_align_batch.argtypes = [
-                P, i64, P, P, P, i64, P, P, P, i32, i64,
-                i32, i32, i32, i32, i32, i32,
-                P, P, P, P, P, P, P, P, i32,
-            ]
-            _lib = lib
+            _lib = bind(ctypes.CDLL(_LIB))
     return _lib
 
 
@@ -71,7 +83,7 @@ def _ptr(a):
 
 def align_batch(ref, win_off, win_len, reads, read_off, read_len, mode=None,
                 scoring=DEFAULT_SCORING, trace=False, cigar_cap=64, default_mode=SEMIGLOBAL,
-                threads=None):
+                threads=None, h0=None, default_h0=0, clip=0):
     """Align every (read, window) pair exactly.
 
     ``ref`` and ``reads`` hold one base code (A0 C1 G2 T3) per byte.  Pair p
@@ -80,6 +92,9 @@ def align_batch(ref, win_off, win_len, reads, read_off, read_len, mode=None,
     score, read_end, ref_end, status and, with ``trace``, read_start,
     ref_start, cigar (n_pairs x cigar_cap words ``len<<4 | op``; M=0, I=1,
     D=2) and n_cigar.  Coordinates are 0-based, half-open, window-relative.
+    Extension pairs (mode 2) start from score ``h0[p]`` (or ``default_h0``)
+    and are clipped unless aligning the whole read scores within ``clip`` of
+    the best early end.
     """
     lib = _load()
     ref = np.ascontiguousarray(ref, dtype=np.uint8)
@@ -93,6 +108,9 @@ def align_batch(ref, win_off, win_len, reads, read_off, read_len, mode=None,
     if mode is not None:
         mode = np.ascontiguousarray(mode, dtype=np.uint8)
         assert len(mode) == n
+    if h0 is not None:
+        h0 = np.ascontiguousarray(h0, dtype=np.int32)
+        assert len(h0) == n
     a, b, o, e = (int(x) for x in scoring)
     out = {
         "score": np.zeros(n, np.int32),
@@ -107,9 +125,9 @@ def align_batch(ref, win_off, win_len, reads, read_off, read_len, mode=None,
         out["n_cigar"] = np.zeros(n, np.int32)
     if threads is None:
         threads = os.cpu_count() or 1
-    rc = lib.oracle_align_batch(
+    rc = lib.oracle_align_batch_ext(
         _ptr(ref), len(ref), _ptr(win_off), _ptr(win_len), _ptr(reads), len(reads),
-        _ptr(read_off), _ptr(read_len), _ptr(mode), int(default_mode), n,
+        _ptr(read_off), _ptr(read_len), _ptr(mode), int(default_mode), _ptr(h0), int(default_h0), int(clip), n,
         a, b, o, e, 1 if trace else 0, int(cigar_cap),
         _ptr(out["score"]), _ptr(out.get("read_start")), _ptr(out["read_end"]),
         _ptr(out.get("ref_start")), _ptr(out["ref_end"]), _ptr(out.get("cigar")),
@@ -121,7 +139,7 @@ def align_batch(ref, win_off, win_len, reads, read_off, read_len, mode=None,
 
 
 def align_pairs(pairs, mode=SEMIGLOBAL, scoring=DEFAULT_SCORING, trace=True, cigar_cap=4096,
-                threads=1):
+                threads=1, h0=None, default_h0=0, clip=0):
     """Convenience wrapper: ``pairs`` is a list of (read_codes, window_codes)."""
     reads = [np.asarray(q, np.uint8) for q, _ in pairs]
     wins = [np.asarray(r, np.uint8) for _, r in pairs]
@@ -133,7 +151,7 @@ def align_pairs(pairs, mode=SEMIGLOBAL, scoring=DEFAULT_SCORING, trace=True, cig
     W = np.concatenate(wins) if wins else np.zeros(0, np.uint8)
     modes = np.full(len(pairs), mode, np.uint8) if np.isscalar(mode) else np.asarray(mode, np.uint8)
     return align_batch(W, win_off, win_len, R, read_off, read_len, modes, scoring, trace,
-                       cigar_cap, threads=threads)
+                       cigar_cap, threads=threads, h0=h0, default_h0=default_h0, clip=clip)
 
 
 def decode_cigar(words, n):

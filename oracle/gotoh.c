@@ -17,6 +17,11 @@
  *     (Methods, architecture section and DP section), hence two modes: semi-global
  *     (whole read against any substring of the window) and local
  *     (Smith-Waterman, both ends free: the clipped ends).
+ *   - the extension mode (mode 2) is the read-extension use of DP with
+ *     clipping: the alignment is anchored at (0,0) with a start score h0 (the
+ *     score of the exact seed it extends), and the read may end early
+ *     (clipped) unless aligning it to its end scores within a clipping
+ *     penalty of the best early end.
  * The paper gives no scores, boundaries, tie-breaks, or CIGAR rules; the
  * readings used here are stated next to each step and listed in the design
  * notes.  Everything is exact int32 arithmetic: every reachable value is far
@@ -41,6 +46,7 @@
 #define ORA_ST_READ_OOB (1u << 4)
 
 #define ORA_MAX_M 1024
+#define ORA_MAX_H0 (1 << 20)
 #define ORA_MAX_N 8192
 
 /* CIGAR op codes as in BAM: M=0, I=1, D=2; a CIGAR word is len<<4 | op */
@@ -56,8 +62,11 @@ typedef struct {
   int64_t reads_len;
   const int64_t *read_off;
   const int32_t *read_len;
-  const uint8_t *mode; /* 0 = semi-global, 1 = local; NULL: default_mode */
+  const uint8_t *mode; /* 0 = semi-global, 1 = local, 2 = extension; NULL: default_mode */
   int32_t default_mode;
+  const int32_t *h0;   /* extension start score per pair; NULL: default_h0 */
+  int32_t default_h0;
+  int32_t clip;        /* extension clipping penalty */
   int64_t n_pairs;
   int32_t a, b, o, e; /* match, mismatch, gap open, gap extend */
   int32_t want_trace; /* compute starts and CIGAR */
@@ -101,10 +110,12 @@ static int ws_reserve(ora_ws_t *w, size_t cells, size_t nops) {
 
 static inline int32_t imax(int32_t x, int32_t y) { return x > y ? x : y; }
 
-/* Align read q[0..m) against window r[0..n) and write the outputs of pair p. */
+/* Align read q[0..m) against window r[0..n) in mode md (0 semi-global,
+ * 1 local, 2 extension with start score h0) and write the outputs of pair p. */
 static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, int m,
-                      const uint8_t *r, int n, int local) {
+                      const uint8_t *r, int n, int md, int32_t h0) {
   const int32_t a = J->a, b = J->b, o = J->o, e = J->e;
+  const int local = md == 1, ext = md == 2;
   const int W1 = n + 1; /* row stride */
   int32_t *H = W->H, *D = W->D, *I = W->I;
 #define AT(X, i, j) X[(size_t)(i) * W1 + (j)]
@@ -113,15 +124,18 @@ static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, in
    * Semi-global: the read is aligned end to end, the window is free at both
    * ends: H(0,j) = 0 for every j; H(i,0) = I(i,0) = -(o + i*e) (a leading
    * insertion before the window); D(i,0) = NEG; D(0,j) = I(0,j) = NEG.
-   * Local: H(0,j) = H(i,0) = 0; D and I are NEG on row 0 and column 0. */
+   * Local: H(0,j) = H(i,0) = 0; D and I are NEG on row 0 and column 0.
+   * Extension: anchored at (0,0) with score h0: H(0,0) = h0; a leading
+   * deletion H(0,j) = D(0,j) = h0 - (o + j*e), I(0,j) = NEG; a leading
+   * insertion H(i,0) = I(i,0) = h0 - (o + i*e), D(i,0) = NEG. */
   for (int j = 0; j <= n; j++) {
-    AT(H, 0, j) = 0;
-    AT(D, 0, j) = ORA_NEG;
+    AT(H, 0, j) = ext ? (j == 0 ? h0 : h0 - (o + j * e)) : 0;
+    AT(D, 0, j) = (ext && j > 0) ? h0 - (o + j * e) : ORA_NEG;
     AT(I, 0, j) = ORA_NEG;
   }
   for (int i = 1; i <= m; i++) {
-    AT(H, i, 0) = local ? 0 : -(o + i * e);
-    AT(I, i, 0) = local ? ORA_NEG : -(o + i * e);
+    AT(H, i, 0) = local ? 0 : (ext ? h0 : 0) - (o + i * e);
+    AT(I, i, 0) = local ? ORA_NEG : (ext ? h0 : 0) - (o + i * e);
     AT(D, i, 0) = ORA_NEG;
   }
 
@@ -149,10 +163,14 @@ static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, in
    * ties to the smallest j.  Local: the largest H over (0,0) (value 0) and
    * every cell with i,j >= 1, ties to the smallest j, then the smallest i.
    * Scanning j outer / i inner and replacing only on a strictly larger
-   * value realises exactly that order. */
+   * value realises exactly that order.
+   * Extension: the best early end is the local rule with (0,0) worth h0;
+   * the best end-to-end end is the semi-global rule on row m; the read is
+   * aligned to its end when that scores at least the early end minus the
+   * clipping penalty, and clipped otherwise. */
   int bi = 0, bj = 0;
   int32_t best;
-  if (!local) {
+  if (md == 0) {
     bi = m;
     best = AT(H, m, 0);
     for (int j = 1; j <= n; j++)
@@ -161,7 +179,7 @@ static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, in
         bj = j;
       }
   } else {
-    best = 0;
+    best = ext ? h0 : 0;
     for (int j = 1; j <= n; j++)
       for (int i = 1; i <= m; i++)
         if (AT(H, i, j) > best) {
@@ -169,6 +187,20 @@ static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, in
           bi = i;
           bj = j;
         }
+    if (ext) {
+      int32_t gbest = AT(H, m, 0);
+      int gj = 0;
+      for (int j = 1; j <= n; j++)
+        if (AT(H, m, j) > gbest) {
+          gbest = AT(H, m, j);
+          gj = j;
+        }
+      if ((int64_t)gbest >= (int64_t)best - J->clip) {
+        best = gbest;
+        bi = m;
+        bj = gj;
+      }
+    }
   }
   J->score[p] = best;
   J->read_end[p] = bi;
@@ -177,7 +209,9 @@ static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, in
 
   /* Traceback from (bi, bj) in state H with priorities
    *   zero (local) > diagonal > D > I, and gap open > gap extend,
-   * decided by equality tests on the stored matrices. */
+   * decided by equality tests on the stored matrices.  An extension ends at
+   * the anchor (0,0): on row 0 the rest is a leading deletion, on column 0
+   * a leading insertion. */
   enum { ST_H, ST_D, ST_I } st = ST_H;
   int i = bi, j = bj;
   size_t nops = 0;
@@ -185,6 +219,10 @@ static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, in
   for (;;) {
     if (st == ST_H) {
       if (local && AT(H, i, j) == 0) break;
+      if (ext && i == 0) {
+        for (; j > 0; j--) ops[nops++] = OP_D;
+        break;
+      }
       if (i == 0) break;
       if (!local && j == 0) {
         for (; i > 0; i--) ops[nops++] = OP_I;
@@ -239,7 +277,8 @@ static void align_one(ora_job_t *J, ora_ws_t *W, int64_t p, const uint8_t *q, in
 
 static void run_pair(ora_job_t *J, ora_ws_t *W, int64_t p) {
   const int32_t m = J->read_len[p], n = J->win_len[p];
-  const int local = (J->mode ? J->mode[p] : J->default_mode) == 1;
+  const int md = J->mode ? J->mode[p] : J->default_mode;
+  const int32_t h0 = J->h0 ? J->h0[p] : J->default_h0;
   J->status[p] = 0;
   J->score[p] = 0;
   J->read_end[p] = 0;
@@ -249,7 +288,7 @@ static void run_pair(ora_job_t *J, ora_ws_t *W, int64_t p) {
     J->ref_start[p] = 0;
     J->n_cigar[p] = 0;
   }
-  if (m < 0 || n < 0 || m > ORA_MAX_M || n > ORA_MAX_N) {
+  if (m < 0 || n < 0 || m > ORA_MAX_M || n > ORA_MAX_N || md < 0 || md > 2 || (md == 2 && (h0 < 0 || h0 > ORA_MAX_H0))) {
     J->status[p] = ORA_ST_LEN_LIMIT;
     return;
   }
@@ -262,7 +301,7 @@ static void run_pair(ora_job_t *J, ora_ws_t *W, int64_t p) {
     return;
   }
   if (ws_reserve(W, (size_t)(m + 1) * (size_t)(n + 1), (size_t)(m + n + 1)) != 0) abort();
-  align_one(J, W, p, J->reads + J->read_off[p], m, J->ref + J->win_off[p], n, local);
+  align_one(J, W, p, J->reads + J->read_off[p], m, J->ref + J->win_off[p], n, md, h0);
 }
 
 static void *worker(void *arg) {
@@ -289,19 +328,21 @@ static void *worker(void *arg) {
 /* Align n_pairs pairs on n_threads host threads (dynamic chunks of 256
  * pairs).  Sequences are one code per byte.  Returns 0, or -1 on invalid
  * scoring.  read_start, ref_start, cigar and n_cigar are used only when
- * want_trace is non-zero; cigar holds cigar_cap words per pair. */
-int oracle_align_batch(const uint8_t *ref, int64_t ref_len, const int64_t *win_off,
-                       const int32_t *win_len, const uint8_t *reads, int64_t reads_len,
-                       const int64_t *read_off, const int32_t *read_len, const uint8_t *mode,
-                       int32_t default_mode, int64_t n_pairs, int32_t match, int32_t mismatch,
-                       int32_t gap_open, int32_t gap_extend, int32_t want_trace,
-                       int32_t cigar_cap, int32_t *score, int32_t *read_start,
-                       int32_t *read_end, int32_t *ref_start, int32_t *ref_end, uint32_t *cigar,
-                       int32_t *n_cigar, uint32_t *status, int32_t n_threads) {
+ * want_trace is non-zero; cigar holds cigar_cap words per pair.  Extension
+ * pairs (mode 2) take their start score from h0[p] (h0 NULL: default_h0)
+ * and the clipping penalty clip. */
+int oracle_align_batch_ext(const uint8_t *ref, int64_t ref_len, const int64_t *win_off,
+                           const int32_t *win_len, const uint8_t *reads, int64_t reads_len,
+                           const int64_t *read_off, const int32_t *read_len, const uint8_t *mode,
+                           int32_t default_mode, const int32_t *h0, int32_t default_h0, int32_t clip,
+                           int64_t n_pairs, int32_t match, int32_t mismatch, int32_t gap_open,
+                           int32_t gap_extend, int32_t want_trace, int32_t cigar_cap, int32_t *score,
+                           int32_t *read_start, int32_t *read_end, int32_t *ref_start, int32_t *ref_end,
+                           uint32_t *cigar, int32_t *n_cigar, uint32_t *status, int32_t n_threads) {
   if (match < 1 || match > 4096 || mismatch > 0 || mismatch < -4096 || gap_open < 0 ||
       gap_open > 4096 || gap_extend < 1 || gap_extend > 4096)
     return -1;
-  if (n_pairs < 0 || cigar_cap < 0) return -1;
+  if (n_pairs < 0 || cigar_cap < 0 || clip < 0 || clip > ORA_MAX_H0) return -1;
   ora_job_t J;
   memset(&J, 0, sizeof(J));
   J.ref = ref;
@@ -314,6 +355,9 @@ int oracle_align_batch(const uint8_t *ref, int64_t ref_len, const int64_t *win_o
   J.read_len = read_len;
   J.mode = mode;
   J.default_mode = default_mode;
+  J.h0 = h0;
+  J.default_h0 = default_h0;
+  J.clip = clip;
   J.n_pairs = n_pairs;
   J.a = match;
   J.b = mismatch;
@@ -342,4 +386,19 @@ int oracle_align_batch(const uint8_t *ref, int64_t ref_len, const int64_t *win_o
   }
   pthread_mutex_destroy(&J.lock);
   return 0;
+}
+
+/* The semi-global / local entry point (no extension parameters). */
+int oracle_align_batch(const uint8_t *ref, int64_t ref_len, const int64_t *win_off,
+                       const int32_t *win_len, const uint8_t *reads, int64_t reads_len,
+                       const int64_t *read_off, const int32_t *read_len, const uint8_t *mode,
+                       int32_t default_mode, int64_t n_pairs, int32_t match, int32_t mismatch,
+                       int32_t gap_open, int32_t gap_extend, int32_t want_trace,
+                       int32_t cigar_cap, int32_t *score, int32_t *read_start,
+                       int32_t *read_end, int32_t *ref_start, int32_t *ref_end, uint32_t *cigar,
+                       int32_t *n_cigar, uint32_t *status, int32_t n_threads) {
+  return oracle_align_batch_ext(ref, ref_len, win_off, win_len, reads, reads_len, read_off, read_len, mode,
+                                default_mode, NULL, 0, 0, n_pairs, match, mismatch, gap_open, gap_extend,
+                                want_trace, cigar_cap, score, read_start, read_end, ref_start, ref_end,
+                                cigar, n_cigar, status, n_threads);
 }

@@ -295,3 +295,85 @@ def canonical_at_least(q, r, mode, sc, floor):
         else:
             runs.append([1, op])
     return best, (ei, ej), (x[1], x[2]), ["%d%s" % (L, "MID"[op]) for L, op in runs]
+
+
+# ---------------------------------------------------------------------------
+# Extension mode: every alignment starts at the anchor (0, 0) with score h0 and
+# ends at any cell (i, j); its score is h0 plus the path score (a leading gap
+# at the anchor is an ordinary gap run).  The best early end is the largest
+# score over (0, 0) and the cells with i, j >= 1 (ties: smallest j, then
+# smallest i); the best end-to-end end is the largest over row m (ties:
+# smallest j).  The read is aligned to its end when that scores at least the
+# early end minus the clipping penalty.
+
+
+def ext_end_scores(q, r, sc, h0):
+    """{(i, j): best score of an anchored alignment ending at (i, j)}."""
+    q = np.asarray(q)[None, :]
+    r = np.asarray(r)[None, :]
+    m, n = q.shape[1], r.shape[1]
+    vals = {}
+    for i in range(m + 1):
+        for j in range(n + 1):
+            vals[(i, j)] = h0 + float(_path_scores(q[:, :i], r[:, :j], sc).max())
+    return vals
+
+
+def ext_best(q, r, sc, h0, clip):
+    """(score, (end_i, end_j)) chosen by the extension rules."""
+    m, n = len(q), len(r)
+    vals = ext_end_scores(q, r, sc, h0)
+    lbest, lcell = float(h0), (0, 0)
+    for j in range(1, n + 1):
+        for i in range(1, m + 1):
+            if vals[(i, j)] > lbest:
+                lbest, lcell = vals[(i, j)], (i, j)
+    gbest, gcell = vals[(m, 0)], (m, 0)
+    for j in range(1, n + 1):
+        if vals[(m, j)] > gbest:
+            gbest, gcell = vals[(m, j)], (m, j)
+    if gbest >= lbest - clip:
+        return int(gbest), gcell
+    return int(lbest), lcell
+
+
+def decisions_ext(ops):
+    """Backward decisions of an anchored alignment: a leading run of one gap
+    kind is walked without choices once the walk reaches row 0 or column 0."""
+    lead = 0
+    if ops and ops[0] != OP_M:
+        while lead < len(ops) and ops[lead] == ops[0]:
+            lead += 1
+    toks = []
+    k = len(ops)
+    while k > lead:
+        op = ops[k - 1]
+        if op == OP_M:
+            toks.append(1)
+            k -= 1
+            continue
+        L = 0
+        while k - L > lead and ops[k - 1 - L] == op:
+            L += 1
+        toks.append(2 if op == OP_D else 3)
+        toks += [1] * (L - 1) + [0]
+        k -= L
+    return tuple(toks)
+
+
+def canonical_ext(q, r, sc, h0, clip):
+    """Score, end cell and run-length CIGAR the extension traceback must give
+    (the start is always the anchor (0, 0))."""
+    q = np.asarray(q)
+    r = np.asarray(r)
+    score, (bi, bj) = ext_best(q, r, sc, h0, clip)
+    ops, _, _, _ = path_table(bi, bj)
+    v = h0 + _path_scores(q[None, :bi], r[None, :bj], sc)[0]
+    cands = sorted((decisions_ext(ops[k]), ops[k]) for k in np.nonzero(v == score)[0])
+    runs = []
+    for op in cands[0][1]:
+        if runs and runs[-1][1] == op:
+            runs[-1][0] += 1
+        else:
+            runs.append([1, op])
+    return score, (bi, bj), ["%d%s" % (L, "MID"[op]) for L, op in runs]

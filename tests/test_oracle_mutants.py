@@ -42,6 +42,14 @@ MUTANTS = {
         "if (AT(I, i, j) != AT(I, i - 1, j) - e) st = ST_H;"),
     "trace_no_local_zero_stop": ("if (local && AT(H, i, j) == 0) break;", "if (local && i == 0) break;"),
     "cigar_I_D_swapped": ("enum { OP_M = 0, OP_I = 1, OP_D = 2 };", "enum { OP_M = 0, OP_I = 2, OP_D = 1 };"),
+    "ext_clip_strict": ("if ((int64_t)gbest >= (int64_t)best - J->clip) {",
+                        "if ((int64_t)gbest > (int64_t)best - J->clip) {"),
+    "ext_row0_gap_without_open": ("AT(H, 0, j) = ext ? (j == 0 ? h0 : h0 - (o + j * e)) : 0;",
+                                  "AT(H, 0, j) = ext ? (j == 0 ? h0 : h0 - j * e) : 0;"),
+    "ext_early_end_ignores_anchor": ("best = ext ? h0 : 0;", "best = 0;"),
+    "ext_col0_without_start_score": ("AT(H, i, 0) = local ? 0 : (ext ? h0 : 0) - (o + i * e);",
+                                     "AT(H, i, 0) = local ? 0 : -(o + i * e);"),
+    "ext_trace_row0_no_deletions": ("for (; j > 0; j--) ops[nops++] = OP_D;", "j = 0;"),
 }
 
 
@@ -62,12 +70,7 @@ def build_mutant(name):
 
 
 def _bind(lib):
-    P = ctypes.c_void_p
-    i64, i32 = ctypes.c_int64, ctypes.c_int32
-    lib.oracle_align_batch.restype = ctypes.c_int
-    lib.oracle_align_batch.argtypes = [P, i64, P, P, P, i64, P, P, P, i32, i64, i32, i32, i32, i32,
-                                       i32, i32, P, P, P, P, P, P, P, P, i32]
-    return lib
+    return oracle.bind(lib)
 
 
 def _brute_small():
@@ -84,11 +87,23 @@ def _brute_small():
                 assert oracle.decode_cigar(got["cigar"][p], got["n_cigar"][p]) == "".join(cig)
 
 
+def _brute_ext_small():
+    import test_oracle_extension as X
+    rng = np.random.default_rng(7)
+    for sc in ((1, -4, 6, 1), (3, 0, 2, 1)):
+        pairs = [(tuple(rng.integers(0, 4, int(rng.integers(0, 5)))), tuple(rng.integers(0, 4, int(rng.integers(0, 5)))))
+                 for _ in range(120)]
+        for h0, clip in ((0, 0), (6, 2), (9, 50)):
+            X._check(pairs, sc, h0, clip)
+    X.test_extension_closed_forms()
+
+
 PINS = [lambda: [P.test_hand_example(row) for row in P.HAND],
         lambda: [P.test_gap_open_extend_tie_case(row) for row in P.TIES],
         P.test_closed_forms,
         P.test_cigar_rescores_to_score_and_spans_coordinates,
-        _brute_small]
+        _brute_small,
+        _brute_ext_small]
 
 
 def pins_pass(lib):
