@@ -30,7 +30,9 @@ PEAK_I16_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Algorithmic integer ops per cell (binary ops, a 3-way max counts 2):
 # semi-global score+end 9, +4 direction compares = 13; local score+best 11, +5 = 16.
-OPS_PER_CELL = {("sg", True): 13, ("sg", False): 9, ("local", True): 16, ("local", False): 11}
+OPS_PER_CELL = {("sg", True): 13, ("sg", False): 9, ("local", True): 16, ("local", False): 11,
+                ("ext", True): 16, ("ext", False): 11}
+EXT_CLIP = 5  # clipping penalty of the seed-extension workload
 
 # HBM bytes per launch of the dominant fill kernel from two rocprofv3 passes
 # (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a 1 GiB
@@ -69,6 +71,8 @@ def make_batch(cfg, pairs):
         return synth.config2(**({"n_pairs": pairs} if pairs else {}))
     if cfg == "c3":
         return synth.config3(**({"n_pairs": pairs} if pairs else {}))
+    if cfg == "ext":
+        return synth.extension_like(pairs or 1_000_000, ref_len=100_000_000)
     raise SystemExit("unknown config " + cfg)
 
 
@@ -80,6 +84,8 @@ WORKLOADS = {
            "score + start/end + CIGAR", "local", True, False),
     "c3": ("2,000,000 pairs, reads U{50..250} bp vs 1.5m+64 bp windows, half local, one persistent "
            "launch, score + start/end + CIGAR", "mixed", True, False),
+    "ext": ("1,000,000 seed extensions: read tails U{0..150} bp vs tail+32 bp windows, anchor score "
+            "U{19..60}, clipping penalty 5, int16 + int32 re-run, score + start/end + CIGAR", "ext", True, False),
 }
 
 
@@ -88,13 +94,17 @@ def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
     import oracle
     threads = min(16, os.cpu_count() or 1)
     sc = (1, -4, 6, 1)
+    h0 = batch.h0 if batch.h0 is not None else np.zeros(batch.n_pairs, np.int32)
+    ext = dict(clip=EXT_CLIP)
     oracle.align_batch(batch.ref, batch.win_off[:64], batch.win_len[:64], batch.reads, batch.read_off[:64],
-                       batch.read_len[:64], batch.mode[:64], sc, trace=want_trace, threads=threads)
+                       batch.read_len[:64], batch.mode[:64], sc, trace=want_trace, threads=threads,
+                       h0=h0[:64], **ext)
     n = min(batch.n_pairs, 20000)
     idx = np.arange(n)
     t0 = time.time()
     o = oracle.align_batch(batch.ref, batch.win_off[idx], batch.win_len[idx], batch.reads, batch.read_off[idx],
-                           batch.read_len[idx], batch.mode[idx], sc, trace=want_trace, threads=threads)
+                           batch.read_len[idx], batch.mode[idx], sc, trace=want_trace, threads=threads,
+                           h0=h0[idx], **ext)
     dt = time.time() - t0
     if dt < target_s / 3 and n < batch.n_pairs:
         n = int(min(batch.n_pairs, n * target_s / max(dt, 1e-3)))
@@ -102,7 +112,7 @@ def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
         t0 = time.time()
         o = oracle.align_batch(batch.ref, batch.win_off[idx], batch.win_len[idx], batch.reads,
                                batch.read_off[idx], batch.read_len[idx], batch.mode[idx], sc,
-                               trace=want_trace, threads=threads)
+                               trace=want_trace, threads=threads, h0=h0[idx], **ext)
         dt = time.time() - t0
     cells = float(np.dot(batch.read_len[idx].astype(np.int64), batch.win_len[idx].astype(np.int64)))
     # parity of the GPU result on the same sample
@@ -290,12 +300,15 @@ def main():
     uniform = bool((batch.mode == batch.mode[0]).all()) if n else True
     mode_arg = None if uniform else dev["mode"]
     default_mode = int(batch.mode[0]) if (uniform and n) else 0
+    mode_mask = int(np.bitwise_or.reduce(1 << np.unique(batch.mode).astype(np.int64))) if n else 0
+    ext_h0 = torch.as_tensor(batch.h0).cuda() if batch.h0 is not None else None
 
     def step():
         mica.align(ctx, dev["ref2b"], dev["win_off"], dev["win_len"], dev["reads2b"], dev["read_off"],
                    dev["read_len"], mode=mode_arg, default_mode=default_mode, out_cigar=want_trace, cigar_cap=cap,
                    force_int32=force_i32, plain=args.plain, max_read_len=max_m, max_win_len=max_n,
-                   ref_len=dev["ref_len"], reads_len=dev["reads_len"], out=out)
+                   ref_len=dev["ref_len"], reads_len=dev["reads_len"], out=out, mode_mask=mode_mask,
+                   ext_h0=ext_h0, ext_clip=EXT_CLIP)
 
     for _ in range(args.warmup):
         step()
@@ -338,7 +351,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "i32" if force_i32 else "i16", "data": "synthetic",
         "config": {"workload": desc, "name": args.config, "pairs": n, "cells": cells,
-                   "launch": "plain per-bucket" if args.plain else "persistent"},
+                   "launch": "plain per-bucket" if args.plain or args.config == "ext" else "persistent"},
         "roofline": roof,
         "saturated_pairs": int(stats["n_saturated"]),
         "resident_waves": int(stats["n_waves"]),

@@ -66,7 +66,14 @@ typedef struct {
   int32_t match, mismatch, gap_open, gap_extend;
 } mica_scoring_t;
 
-enum { MICA_MODE_SEMIGLOBAL = 0, MICA_MODE_LOCAL = 1 };
+/* Modes.  MICA_MODE_EXTEND is the read-extension use of DP with clipping:
+ * the alignment is anchored at (0,0) with a start score h0 (the score of the
+ * seed it extends; a leading gap at the anchor is an ordinary gap run), the
+ * best early end is taken as in local mode with (0,0) worth h0, the best
+ * end-to-end end as in semi-global mode on row m, and the read is aligned to
+ * its end when that scores at least the early end minus the clipping
+ * penalty (else it is clipped).  Starts are always (0,0). */
+enum { MICA_MODE_SEMIGLOBAL = 0, MICA_MODE_LOCAL = 1, MICA_MODE_EXTEND = 2 };
 
 /* flags of mica_dp_align_batch */
 enum {
@@ -81,7 +88,7 @@ enum {
 enum {
   MICA_ST_SATURATED = 1u << 0,   /* 16-bit scores saturated; the 32-bit re-run result is final */
   MICA_ST_CIGAR_TRUNC = 1u << 1, /* n_cigar = -(runs needed); cigar holds the first cigar_cap runs */
-  MICA_ST_LEN_LIMIT = 1u << 2,   /* m or n outside [0, max_*_len], or mode not 0/1: not computed */
+  MICA_ST_LEN_LIMIT = 1u << 2,   /* m or n outside [0, max_*_len], mode not 0/1/2 (or outside mode_mask), or h0 out of range */
   MICA_ST_WIN_OOB = 1u << 3,     /* window not inside the reference: not computed */
   MICA_ST_READ_OOB = 1u << 4,    /* read not inside the read buffer: not computed */
   MICA_ST_INTERNAL = 1u << 5     /* a device consistency check failed; coordinates and CIGAR invalid */
@@ -133,6 +140,16 @@ typedef struct {
   int32_t cigar_cap;
   int32_t *n_cigar; /* required with MICA_OUT_CIGAR */
   uint32_t *status; /* always written */
+  /* extension mode: start score per pair (NULL: ext_default_h0), 0..2^20,
+   * and the clipping penalty, 0..2^20 */
+  const int32_t *ext_h0;
+  int32_t ext_default_h0;
+  int32_t ext_clip;
+  /* with a per-pair mode array: bit MICA_MODE_x set for every mode the
+   * array may hold, 0 = any of the three.  Kernels of absent modes are not
+   * launched; a pair whose mode is outside the mask gets MICA_ST_LEN_LIMIT.
+   * Ignored without a mode array. */
+  int32_t mode_mask;
 } mica_batch_t;
 
 /* Align every pair of `batch` (Methods, DP section; readings above).

@@ -16,14 +16,14 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (FORCE_INT32, MAX_READ_LEN, MAX_WIN_LEN, MODE_LOCAL, MODE_SEMIGLOBAL, NO_GRAPH,
+from ._lib import (FORCE_INT32, MAX_READ_LEN, MAX_WIN_LEN, MODE_EXTEND, MODE_LOCAL, MODE_SEMIGLOBAL, NO_GRAPH,
                    OUT_CIGAR, OUT_START, PLAIN_LAUNCH, ST_CIGAR_TRUNC, ST_LEN_LIMIT, ST_READ_OOB,
                    ST_SATURATED, ST_WIN_OOB, MicaError)
 from .pack import pack_codes, unpack_words
 from .serve import Server
 
 __all__ = ["Context", "Server", "align", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
-           "PLAIN_LAUNCH", "NO_GRAPH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "ST_SATURATED",
+           "PLAIN_LAUNCH", "NO_GRAPH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "MODE_EXTEND", "ST_SATURATED",
            "ST_CIGAR_TRUNC", "ST_LEN_LIMIT", "ST_WIN_OOB", "ST_READ_OOB", "MAX_READ_LEN", "MAX_WIN_LEN"]
 
 
@@ -129,7 +129,7 @@ def pack_2bit(codes, stream=None):
 
 def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring, out_start, out_cigar,
                 cigar_cap, force_int32, plain, graph, default_mode, max_read_len, max_win_len, ref_len,
-                reads_len, out, outputs=True):
+                reads_len, out, outputs=True, ext_h0=None, ext_default_h0=0, ext_clip=0, mode_mask=0):
     ref2b = _dev(ref2b, torch.int32, "ref2b")
     reads2b = _dev(reads2b, torch.int32, "reads2b")
     win_off = _dev(win_off, torch.int64, "win_off")
@@ -143,6 +143,10 @@ def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scor
         mode = _dev(mode, torch.uint8, "mode")
         if mode.numel() != n:
             raise ValueError("mode must have one entry per pair")
+    if ext_h0 is not None:
+        ext_h0 = _dev(ext_h0, torch.int32, "ext_h0")
+        if ext_h0.numel() != n:
+            raise ValueError("ext_h0 must have one entry per pair")
     if max_read_len is None:
         max_read_len = int(read_len.max().item()) if n else 0
     if max_win_len is None:
@@ -186,6 +190,10 @@ def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scor
     b.cigar_cap = int(cigar_cap) if out_cigar else 0
     b.n_cigar = _ptr(out.get("n_cigar"))
     b.status = _ptr(out.get("status"))
+    b.ext_h0 = _ptr(ext_h0)
+    b.ext_default_h0 = int(ext_default_h0)
+    b.ext_clip = int(ext_clip)
+    b.mode_mask = int(mode_mask)
     a_, b_, o_, e_ = (int(x) for x in scoring)
     sc = _lib.Scoring(a_, b_, o_, e_)
     flags = (OUT_START if out_start else 0) | (OUT_CIGAR if out_cigar else 0) | \
@@ -196,7 +204,8 @@ def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scor
 def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, scoring=(1, -4, 6, 1),
           out_start=False, out_cigar=False, cigar_cap=64, force_int32=False, plain=False, graph=True,
           default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
-          reads_len=None, out=None, stream=None):
+          reads_len=None, out=None, stream=None, ext_h0=None, ext_default_h0=0, ext_clip=0,
+          mode_mask=0):
     """Align every (read, window) pair on the GPU; returns a dict of tensors.
 
     ref2b / reads2b: int32 tensors of 2-bit packed bases; win_off / read_off:
@@ -205,11 +214,17 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
     status and, when requested, read_start, ref_start, cigar, n_cigar.
     ``max_read_len`` / ``max_win_len`` default to the batch maxima (one host
     synchronisation).  ``graph=False`` enqueues the kernels one by one
-    instead of as one HIP graph.  The call is asynchronous on ``stream``.
+    instead of as one HIP graph.  Extension pairs (mode 2) start from
+    ``ext_h0`` (int32 per pair) or ``ext_default_h0`` and are clipped unless
+    the whole read scores within ``ext_clip`` of the best early end.
+    ``mode_mask`` (bit per mode, 0 = all) names the modes a ``mode`` array
+    may hold, so kernels of absent modes are not launched.  The
+    call is asynchronous on ``stream``.
     """
     b, sc, flags, out = _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring,
                                     out_start, out_cigar, cigar_cap, force_int32, plain, graph, default_mode,
-                                    max_read_len, max_win_len, ref_len, reads_len, out)
+                                    max_read_len, max_win_len, ref_len, reads_len, out, ext_h0=ext_h0,
+                                    ext_default_h0=ext_default_h0, ext_clip=ext_clip, mode_mask=mode_mask)
     _lib.check(_lib.load().mica_dp_align_batch(ctx.handle, ctypes.byref(b), ctypes.byref(sc), flags,
                                                _stream_handle(stream)))
     return out

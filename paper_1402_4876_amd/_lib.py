@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "MICA_OK", -1: "MICA_ERR_INVALID_ARG", -2: "MICA_ERR_LIMIT",
 
 MODE_SEMIGLOBAL = 0
 MODE_LOCAL = 1
+MODE_EXTEND = 2
 OUT_START = 1 << 0
 OUT_CIGAR = 1 << 1
 FORCE_INT32 = 1 << 8
@@ -59,6 +60,8 @@ class Batch(ctypes.Structure):
         ("read_start", ctypes.c_void_p), ("ref_start", ctypes.c_void_p),
         ("cigar", ctypes.c_void_p), ("cigar_cap", ctypes.c_int32),
         ("n_cigar", ctypes.c_void_p), ("status", ctypes.c_void_p),
+        ("ext_h0", ctypes.c_void_p), ("ext_default_h0", ctypes.c_int32), ("ext_clip", ctypes.c_int32),
+        ("mode_mask", ctypes.c_int32),
     ]
 
 

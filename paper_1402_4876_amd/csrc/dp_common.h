@@ -9,6 +9,7 @@ namespace mica {
 
 constexpr int kMaxM = 1024;  // longest read (rows)
 constexpr int kMaxN = 8192;  // longest window (columns)
+constexpr int kMaxH0 = 1 << 20;  // largest extension anchor score and clipping penalty
 
 // Kernel classes: class c < 16 runs 16 lanes per pair with c+1 read rows per
 // lane (reads up to 16*(c+1) bases); classes 16, 17 and 18 run a whole wave
@@ -28,13 +29,15 @@ __host__ __device__ constexpr int class_of(int lanes, int rows) {
 // 16-bit with a run-time saturation check, and 32-bit.
 enum Kind : int { kK16 = 0, kK16Sat = 1, kK32 = 2 };
 constexpr int kNumKinds = 3;
-constexpr int kNumBuckets = kNumKinds * kNumClasses * 2;
+// alignment modes: 0 semi-global, 1 local, 2 seed extension with clipping
+constexpr int kNumModes = 3;
+constexpr int kNumBuckets = kNumKinds * kNumClasses * kNumModes;
 __host__ __device__ constexpr int bucket_id(int kind, int cls, int mode) {
-  return (kind * kNumClasses + cls) * 2 + mode;
+  return (kind * kNumClasses + cls) * kNumModes + mode;
 }
-__host__ __device__ constexpr int bucket_kind(int b) { return b / (2 * kNumClasses); }
-__host__ __device__ constexpr int bucket_class(int b) { return (b / 2) % kNumClasses; }
-__host__ __device__ constexpr int bucket_mode(int b) { return b & 1; }
+__host__ __device__ constexpr int bucket_kind(int b) { return b / (kNumModes * kNumClasses); }
+__host__ __device__ constexpr int bucket_class(int b) { return (b / kNumModes) % kNumClasses; }
+__host__ __device__ constexpr int bucket_mode(int b) { return b % kNumModes; }
 // pairs handled by one wave-sized work item
 __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
   return (kind == kK32 ? 1 : 2) * (64 / class_lanes(cls));
@@ -51,7 +54,8 @@ __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
 constexpr int kPersistSmallMax = 9;
 constexpr int kPersistMaxClass = MICA_PERSIST_MAX_CLASS;
 __host__ __device__ constexpr bool persistent_bucket(int b) {
-  return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16 && bucket_class(b) <= kPersistMaxClass;
+  return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16 && bucket_class(b) <= kPersistMaxClass &&
+         bucket_mode(b) < 2;
 }
 __host__ __device__ constexpr int persist_part(int cls) { return cls <= kPersistSmallMax ? 0 : 1; }
 // queue part of a persistent (mode, part): the long-read part of a mode
@@ -113,6 +117,10 @@ struct Params {
   int32_t* n_cigar;
   uint32_t* status;
   int32_t sa, sb, so, se;  // match, mismatch, gap open, gap extend
+  const int32_t* ext_h0;   // extension start score per pair (NULL: ext_default_h0)
+  int32_t ext_default_h0;
+  int32_t ext_clip;        // extension clipping penalty
+  int32_t mode_mask;       // modes the batch may hold (bit per mode)
   uint32_t flags;
   // workspace (device memory of the context)
   uint32_t* bucket_of;         // [n_pairs]

@@ -170,7 +170,7 @@ __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool d
   if (class_lanes(cls) == 64 && r == 16) return 2;
   if (kind == kK32) {
     if (mode == 0) return r <= 8 ? 5 : (r <= 11 ? 4 : 3);
-    return dir ? (r <= 5 ? 5 : (r <= 8 ? 4 : (r <= 12 ? 3 : 2))) : (r <= 6 ? 5 : (r <= 10 ? 4 : 3));
+    return dir ? (r <= 5 ? 5 : (r <= 8 ? 4 : (r <= 12 ? 3 : 2))) : (r <= 6 ? 5 : (r <= 10 ? 4 : (r <= 13 || mode == 1 ? 3 : 2)));
   }
   const int sat = kind == kK16Sat ? 1 : 0;
   if (mode == 0) {
@@ -178,7 +178,8 @@ __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool d
     return r <= 6 - sat ? 5 : (r <= 12 - 3 * sat ? 4 : (r <= 16 - 2 * sat ? 3 : 2));
   }
   if (dir) return r <= 3 - sat ? 5 : (r <= 6 - sat ? 4 : (r <= 10 - 2 * sat ? 3 : (r <= 15 || !sat ? 2 : 1)));
-  return r <= 4 - sat ? 5 : (r <= 8 - sat ? 4 : (r <= 12 - sat ? 3 : 2));
+  const int ext = mode == 2 ? 1 : 0;  // the extension also tracks its top boundary
+  return r <= 4 - sat ? 5 : (r <= 8 - sat ? 4 : (r <= 12 - sat - ext ? 3 : 2));
 }
 #ifdef MICA_FILL_WAVES
 #define MICA_BUCKET_WAVES(kind, cls, mode, dir) MICA_FILL_WAVES
@@ -213,6 +214,12 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   constexpr int NP = V::kPairs;
   constexpr int PR = P * R;
   constexpr bool LOCAL = (MODE == 1);
+  // Extension: the read occupies the top m row slots (rows below it compute
+  // values nothing reads), the top boundary is the anchor's leading-deletion
+  // row h0 - (o + j*e), values are not shifted (d0 = 0); the best cell is
+  // tracked per row as in local mode.
+  constexpr bool EXT = (MODE == 2);
+  constexpr bool TRACK = (MODE != 0);
   const int lane = threadIdx.x & 63;
   const int g = lane / P;
   const int k = lane % P;
@@ -224,12 +231,13 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   npairs = uni(npairs);
 
   // ---- the pairs of this lane's group --------------------------------------
-  int pid[NP], m[NP], n[NP], d0[NP];
+  int pid[NP], m[NP], n[NP], d0[NP], h0[NP];
   uint64_t woff[NP], roff[NP];
 #pragma unroll
   for (int h = 0; h < NP; ++h) {
     const int idx = g * NP + h;
     pid[h] = -1;
+    h0[h] = 0;
     m[h] = PR;
     n[h] = 0;
     woff[h] = 0;
@@ -241,8 +249,9 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
       n[h] = G(prm->win_len)[p];
       woff[h] = G(prm->win_off)[p];
       roff[h] = G(prm->read_off)[p];
+      if constexpr (EXT) h0[h] = prm->ext_h0 ? G(prm->ext_h0)[p] : prm->ext_default_h0;
     }
-    d0[h] = PR - m[h];
+    d0[h] = EXT ? 0 : PR - m[h];
   }
   // column range of the item (uniform loop, scalar loads)
   int nmin = 1 << 30, nmax = 0;
@@ -262,7 +271,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     uint32_t q = 0;
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
-      if (u < d0[h] || pid[h] < 0) {
+      if ((EXT ? u >= m[h] : u < d0[h]) || pid[h] < 0) {
         q |= V::qdummy(h);
       } else {
         q |= V::qcode(base_at(reads2b, roff[h] + (uint64_t)(u - d0[h])), h);
@@ -277,14 +286,17 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   // per row: H, and E = the next column's deletion candidate
   // max(D - e, H - o - e) (D and T = H - o - e are not kept)
   T H[R], E[R];
-  T bb[LOCAL ? R : 1], cc[LOCAL ? R : 1];
+  T bb[TRACK ? R : 1], cc[TRACK ? R : 1];
   int hv[NP];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int u = k * R + r;
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
-      if (u < d0[h]) {
+      if constexpr (EXT) {
+        // leading insertion at the anchor (rows below the read continue it)
+        hv[h] = h0[h] - (so + (u + 1) * se);
+      } else if (u < d0[h]) {
         hv[h] = -(u + 1);
       } else {
         const int i = u - d0[h] + 1;
@@ -311,6 +323,15 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
       cc[r] = (T)0;
     }
   }
+  if constexpr (EXT) {
+    // every row's best starts at its column 0 (the end-to-end candidate of
+    // row m covers j = 0; elsewhere column 0 is below h0 and never wins)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      bb[r] = H[r];
+      cc[r] = (T)0;
+    }
+  }
   T hmax = (T)0, tmin = (T)0;
   if constexpr (SAT) {
     hmax = V::splat(-32768);
@@ -321,7 +342,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   // semi-global best over row m: key (score << 16 | 0xFFFF - j), or (score, j)
   int32_t best_key[NP];
   int32_t best_h32 = 0, best_j32 = 0;
-  if constexpr (!LOCAL) {
+  if constexpr (MODE == 0) {
     if constexpr (NP == 2) {
       best_key[0] = (int32_t)((H[R - 1] << 16) | 0xFFFFu);
       best_key[1] = (int32_t)((H[R - 1] & 0xFFFF0000u) | 0xFFFFu);
@@ -341,11 +362,23 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 
   const T ev = V::splat(se);
   const T oev = V::splat(oe);
-  const T tbound = V::splat(-oe);
+  // T and H of the row above the first lane's top row: the top boundary
+  // (0 above the dummy rows; for an extension the anchor row h0 - (o + j*e),
+  // whose T moves down by e per step)
+  T tbound = V::splat(-oe);
   const T negv = (T)V::kNeg;
   T t_last = E[R - 1];  // T of the bottom row, column 0
   T i_last = negv;
   T hdiag_next = (T)0;
+  if constexpr (EXT) {
+    if constexpr (NP == 2) {
+      tbound = V::make2(h0[0] - so - se - oe, h0[1] - so - se - oe);
+      hdiag_next = V::make2(h0[0], h0[1]);
+    } else {
+      tbound = (T)(h0[0] - so - se - oe);
+      hdiag_next = (T)h0[0];
+    }
+  }
   T nn_v = (T)0;
   if constexpr (NP == 2) nn_v = V::make2(n[0], n[1]);
   const uint32_t kk16 = (uint32_t)k * 0x10001u;
@@ -379,7 +412,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     uint32_t acc[4] = {0u, 0u, 0u, 0u};
     if (!CHECK || j >= 1) {
       T jj = (T)0, vmask = (T)0;
-      if constexpr (LOCAL) {
+      if constexpr (TRACK) {
         if constexpr (NP == 2) {
           jj = (uint32_t)(t + 1) * 0x10001u - kk16;
           if constexpr (CHECK) vmask = ~V::negmask(V::sub(nn_v, jj));
@@ -416,7 +449,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             acc[w + 1] = bfi_op(low, acc[w + 1], s23);
           }
         }
-        if constexpr (LOCAL) {
+        if constexpr (TRACK) {
           if constexpr (NP == 2) {
             uint32_t msk = V::negmask(V::sub(bb[r], h));
             if constexpr (CHECK) msk &= vmask;
@@ -445,6 +478,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
       i_last = iup;
       t_last = tup;
     }
+    if constexpr (EXT) {
+      if constexpr (SAT) tmin = V::vmin(tmin, tbound);
+      tbound = V::sub(tbound, ev);
+    }
     if (((t + 2) & (kRing / 2 - 1)) == 0) fill_ring(t + 2);
     rs_b = ring[(t + 2 - k) & (kRing - 1)];
     if constexpr (DIR) {
@@ -453,7 +490,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
       else
         dir2[t * 64 + lane] = (u32x2){acc[0], acc[1]};
     }
-    if constexpr (!LOCAL) {
+    if constexpr (MODE == 0) {
       // row m sits in the last register of the last lane: column t - P + 2
       const int jl = t - P + 2;
       if (jl >= 1) {
@@ -492,7 +529,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 
   // ---- result cell ------------------------------------------------------------
   // red[(g*NP + h)*4 + {0,1,2}] = shifted score, i*, j*
-  if constexpr (!LOCAL) {
+  if constexpr (MODE == 0) {
     if (k == P - 1) {
 #pragma unroll
       for (int h = 0; h < NP; ++h) {
@@ -510,14 +547,18 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
       }
     }
   } else {
-    // per lane: best over its real rows, order (score desc, j asc, i asc)
+    // per lane: best over its real rows, order (score desc, j asc, i asc);
+    // the start cell (0,0) is worth 0 (local, shifted by -d0) or h0
+    // (extension).  An extension's lane holding row m also leaves that row's
+    // best (the end-to-end candidate) in gsl.
+    uint32_t* gsl = red + 64;
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
-      int b0 = -d0[h], c0 = 0, i0 = 0;
+      int b0 = EXT ? h0[h] : -d0[h], c0 = 0, i0 = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int u = k * R + r;
-        if (u >= d0[h]) {
+        if (EXT ? u < m[h] : u >= d0[h]) {
           int bv, cv;
           if constexpr (NP == 2) {
             bv = V::get(bb[r], h);
@@ -532,6 +573,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             c0 = cv;
             i0 = iv;
           }
+          if (EXT && u == m[h] - 1) {
+            gsl[(g * NP + h) * 2 + 0] = (uint32_t)bv;
+            gsl[(g * NP + h) * 2 + 1] = (uint32_t)cv;
+          }
         }
       }
       cand[(lane * NP + h) * 3 + 0] = (uint32_t)b0;
@@ -543,7 +588,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     if (k == P - 1) {
 #pragma unroll
       for (int h = 0; h < NP; ++h) {
-        int b0 = -d0[h], c0 = 0, i0 = 0;
+        int b0 = EXT ? h0[h] : -d0[h], c0 = 0, i0 = 0;
         for (int kk = 0; kk < P; ++kk) {
           const int src = (g * P + kk) * NP + h;
           const int bv = (int)cand[src * 3 + 0], cv = (int)cand[src * 3 + 1], iv = (int)cand[src * 3 + 2];
@@ -556,6 +601,16 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         fb[h] = b0;
         fc[h] = c0;
         fi[h] = i0;
+        if constexpr (EXT) {
+          // end to end when that is within the clipping penalty of the early end
+          const int gv = m[h] > 0 ? (int)gsl[(g * NP + h) * 2 + 0] : h0[h];
+          const int gc = m[h] > 0 ? (int)gsl[(g * NP + h) * 2 + 1] : 0;
+          if ((long)gv >= (long)b0 - (long)prm->ext_clip) {
+            fb[h] = gv;
+            fc[h] = gc;
+            fi[h] = m[h];
+          }
+        }
       }
     }
     lds_wait();
@@ -596,7 +651,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     const int n_ = G(prm->win_len)[p_];
     const uint64_t wo_ = G(prm->win_off)[p_];
     const uint64_t ro_ = G(prm->read_off)[p_];
-    const int d0_ = PR - m_;
+    const int d0_ = EXT ? 0 : PR - m_;
     bool sat_;
     if constexpr (NP == 2) sat_ = h ? sat_h[1] : sat_h[0];
     else sat_ = sat_h[0];
@@ -647,8 +702,14 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
           while (!bad) {
             if (state == 0) {
               if (LOCAL && hval == 0) break;
-              if (i == 0) break;
-              if (!LOCAL && j == 0) {
+              if (i == 0) {
+                if (EXT && j > 0) {  // an extension starts at the anchor: a leading deletion
+                  emit(2, j);
+                  j = 0;
+                }
+                break;
+              }
+              if (!LOCAL && j == 0) {  // a leading insertion (semi-global, extension)
                 emit(1, i);
                 i = 0;
                 break;

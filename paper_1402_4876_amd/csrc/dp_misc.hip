@@ -19,7 +19,8 @@ __global__ __launch_bounds__(256) void k_rerun(const Params* __restrict__ prm) {
     const uint32_t* pp = prm->rerun + it;
     const int p = (int)*pp;
     const int md = prm->mode ? prm->mode[p] : prm->default_mode;
-    if (md) process_item<V32, 64, 16, 1, DIR, false>(prm, pp, 1, lds, slot);
+    if (md == 2) process_item<V32, 64, 16, 2, DIR, false>(prm, pp, 1, lds, slot);
+    else if (md == 1) process_item<V32, 64, 16, 1, DIR, false>(prm, pp, 1, lds, slot);
     else process_item<V32, 64, 16, 0, DIR, false>(prm, pp, 1, lds, slot);
     if ((threadIdx.x & 63) == 0) prm->status[p] |= kStSaturated;
   }
@@ -38,9 +39,22 @@ __global__ void k_zero(const Params* __restrict__ prm) {
   if (i < kNumCounters) prm->counters[i] = 0;
 }
 
-__device__ __forceinline__ bool int16_safe(int m, int n, int mode, int d0, int a, int b, int o, int e) {
-  const long hi = (long)a * (long)(m < n ? m : n) - d0;
-  const long lo = (mode ? -(long)(o + e) : -(long)(2 * o + (long)(m + 1) * e)) - d0;
+// Can every value of the pair's DP stay inside int16 (with a guard band)?
+// Semi-global and local values are shifted by -d0 (dummy rows above the
+// read).  An extension starts from h0: no cell exceeds h0 + a min(m, n),
+// and every cell is at least what the path of j deletions along row 0 and i
+// insertions down column j gives, h0 - 2o - (i + j)e, so every H, gap and
+// boundary value is at least h0 - 3o - (m + n + 1)e.  (Rows below the read
+// only feed rows further below; their values may clamp.)
+__device__ __forceinline__ bool int16_safe(int m, int n, int mode, int d0, int a, int b, int o, int e, int h0) {
+  long hi, lo;
+  if (mode == 2) {
+    hi = (long)h0 + (long)a * (long)(m < n ? m : n);
+    lo = (long)h0 - 3L * o - (long)(m + n + 1) * e;
+  } else {
+    hi = (long)a * (long)(m < n ? m : n) - d0;
+    lo = (mode ? -(long)(o + e) : -(long)(2 * o + (long)(m + 1) * e)) - d0;
+  }
   (void)b;
   return hi <= 32767 - 8 && lo >= -32767 + 8;
 }
@@ -54,19 +68,27 @@ __global__ __launch_bounds__(256) void k_plan(const Params* __restrict__ prm) {
     const int m = prm->read_len[p], n = prm->win_len[p];
     const int md = prm->mode ? (int)prm->mode[p] : prm->default_mode;
     const uint64_t wo = prm->win_off[p], ro = prm->read_off[p];
+    const int h0 = md == 2 ? (prm->ext_h0 ? prm->ext_h0[p] : prm->ext_default_h0) : 0;
     uint32_t st = 0;
-    if (m < 0 || n < 0 || m > prm->max_m || n > prm->max_n) st = kStLenLimit;
+    if (m < 0 || n < 0 || m > prm->max_m || n > prm->max_n || md < 0 || md > 2 || !((prm->mode_mask >> md) & 1) ||
+        h0 < 0 || h0 > kMaxH0)
+      st = kStLenLimit;
     else if (wo > prm->ref_len || (uint64_t)n > prm->ref_len - wo) st = kStWinOob;
     else if (ro > prm->reads_len || (uint64_t)m > prm->reads_len - ro) st = kStReadOob;
-    else if (md != 0 && md != 1) st = kStLenLimit;
     const bool want_start = (prm->flags & (kOutStart | kOutCigar)) != 0;
     const bool want_cigar = (prm->flags & kOutCigar) != 0;
     uint32_t b = kSkip;
     if (st != 0 || m == 0 || n == 0) {
       int score = 0, re = 0;
       int ncig = 0;
-      if (st == 0 && md == 0 && m > 0) {  // semi-global against an empty window
-        score = -(prm->so + m * prm->se);
+      // semi-global against an empty window: all insertions; an extension
+      // with an empty read or window: the anchor itself, or (empty window)
+      // all insertions when that is within the clipping penalty
+      const bool all_ins = st == 0 && m > 0 &&
+                           (md == 0 || (md == 2 && (long)prm->so + (long)m * prm->se <= (long)prm->ext_clip));
+      if (st == 0 && md == 2) score = h0;
+      if (all_ins) {
+        score = (md == 2 ? h0 : 0) - (prm->so + m * prm->se);
         re = m;
         ncig = 1;
         if (want_cigar) {
@@ -88,7 +110,7 @@ __global__ __launch_bounds__(256) void k_plan(const Params* __restrict__ prm) {
       const int d0 = class_lanes(cls) * class_rows(cls) - m;
       int kind;
       if (prm->flags & kForceInt32) kind = kK32;
-      else kind = int16_safe(m, n, md, d0, prm->sa, prm->sb, prm->so, prm->se) ? kK16 : kK16Sat;
+      else kind = int16_safe(m, n, md, d0, prm->sa, prm->sb, prm->so, prm->se, h0) ? kK16 : kK16Sat;
       b = (uint32_t)bucket_id(kind, cls, md);
       atomicAdd(&hist[b], 1u);
     }
@@ -160,7 +182,8 @@ namespace mica {
 #define MICA_FILL_ALL(X) \
   X(k16, 0, 0) X(k16, 0, 1) X(k16, 1, 0) X(k16, 1, 1) \
   X(k16s, 0, 0) X(k16s, 0, 1) X(k16s, 1, 0) X(k16s, 1, 1) \
-  X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1)
+  X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1) \
+  X(k16, 2, 0) X(k16, 2, 1) X(k16s, 2, 0) X(k16s, 2, 1) X(k32, 2, 0) X(k32, 2, 1)
 MICA_FILL_ALL(MICA_FILL_DECL)
 #define MICA_PERSIST_ALL(X) X(0, 0, 0) X(0, 0, 1) X(0, 1, 0) X(0, 1, 1) X(1, 0, 0) X(1, 0, 1) X(1, 1, 0) X(1, 1, 1)
 #define MICA_PERSIST_DECL(dir, mode, part) void reg_persistent_##dir##_##mode##_##part(KernelTable& t);

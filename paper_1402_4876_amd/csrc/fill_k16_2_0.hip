@@ -1,0 +1,8 @@
+// Per-bucket fill kernels: packed 16-bit scores, seed extension, score and end only.
+#include "dp_fill.h"
+
+namespace mica {
+void reg_fill_k16_2_0(KernelTable& t) {
+  fill_bucket_table<false, kK16, 2>(t.bucket[0], ClassSeq{});
+}
+}  // namespace mica

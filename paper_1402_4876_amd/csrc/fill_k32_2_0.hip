@@ -1,0 +1,8 @@
+// Per-bucket fill kernels: 32-bit scores, seed extension, score and end only.
+#include "dp_fill.h"
+
+namespace mica {
+void reg_fill_k32_2_0(KernelTable& t) {
+  fill_bucket_table<false, kK32, 2>(t.bucket[0], ClassSeq{});
+}
+}  // namespace mica

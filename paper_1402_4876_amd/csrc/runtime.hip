@@ -309,7 +309,10 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     return fail(MICA_ERR_INVALID_ARG, "scoring outside its limits");
   if (b->n_pairs < 0) return fail(MICA_ERR_INVALID_ARG, "n_pairs < 0");
   if (b->n_pairs > 0xFFFFFFF0ll) return fail(MICA_ERR_LIMIT, "too many pairs in one batch");
-  if (b->default_mode != 0 && b->default_mode != 1) return fail(MICA_ERR_INVALID_ARG, "bad default_mode");
+  if (b->default_mode < 0 || b->default_mode > 2) return fail(MICA_ERR_INVALID_ARG, "bad default_mode");
+  if (b->mode_mask < 0 || b->mode_mask > 7) return fail(MICA_ERR_INVALID_ARG, "bad mode_mask");
+  if (b->ext_clip < 0 || b->ext_clip > kMaxH0 || b->ext_default_h0 < 0 || b->ext_default_h0 > kMaxH0)
+    return fail(MICA_ERR_INVALID_ARG, "extension start score or clipping penalty outside 0..2^20");
   if (b->max_read_len < 0 || b->max_read_len > kMaxM || b->max_win_len < 0 || b->max_win_len > kMaxN)
     return fail(MICA_ERR_LIMIT, "max_read_len / max_win_len beyond the library limits");
   const bool want_cigar = flags & MICA_OUT_CIGAR;
@@ -333,9 +336,12 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   const int max_m = b->max_read_len, max_n = b->max_win_len;
   const int d = (want_cigar || (flags & MICA_OUT_START)) ? 1 : 0;
   const bool forced = flags & MICA_FORCE_INT32;
-  const bool any_local = b->mode ? true : b->default_mode == 1;
-  const bool any_sg = b->mode ? true : b->default_mode == 0;
-  const bool may_sat = !forced && !int16_always_safe(max_m, max_n, *s, any_local, any_sg);
+  const int mode_mask = b->mode ? (b->mode_mask ? b->mode_mask : 7) : 1 << b->default_mode;
+  const bool any_sg = mode_mask & 1, any_local = mode_mask & 2, any_ext = mode_mask & 4;
+  const bool any_mode[3] = {any_sg, any_local, any_ext};
+  // extensions start from per-pair scores the host does not read: their
+  // saturating variants are always available
+  const bool may_sat = !forced && (any_ext || !int16_always_safe(max_m, max_n, *s, any_local, any_sg));
   const bool plain = flags & MICA_PLAIN_LAUNCH;
   bool cls_used[kNumClasses] = {};
   for (int m = 1; m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
@@ -346,7 +352,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     for (int cls = 0; cls <= kPersistMaxClass; ++cls)
       if (cls_used[cls] && class_lanes(cls) == 16) part_used[persist_part(cls)] = true;
     for (int md = 0; md < 2; ++md) {
-      if ((md == 0 && !any_sg) || (md == 1 && !any_local)) continue;
+      if (!any_mode[md]) continue;
       for (int part : {1, 0})
         if (part_used[part]) fills.push_back(K.persistent[d][md][part]);
     }
@@ -358,8 +364,8 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     if (kind == kK16Sat && !may_sat) continue;
     for (int cls = 0; cls < kNumClasses; ++cls) {
       if (!cls_used[cls]) continue;
-      for (int md = 0; md < 2; ++md) {
-        if ((md == 1 && !any_local) || (md == 0 && !any_sg)) continue;
+      for (int md = 0; md < kNumModes; ++md) {
+        if (!any_mode[md]) continue;
         const int bk = bucket_id(kind, cls, md);
         if (!plain && persistent_bucket(bk)) continue;
         fills.push_back(K.bucket[d][bk]);
@@ -416,6 +422,10 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.read_len = b->read_len;
   P.mode = b->mode;
   P.default_mode = b->default_mode;
+  P.ext_h0 = b->ext_h0;
+  P.ext_default_h0 = b->ext_default_h0;
+  P.ext_clip = b->ext_clip;
+  P.mode_mask = mode_mask;
   P.max_m = max_m;
   P.max_n = max_n;
   P.n_pairs = b->n_pairs;

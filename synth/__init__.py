@@ -46,6 +46,7 @@ class Batch:
     planted_end: np.ndarray | None = None
     planted_ops: list | None = None  # per read: list of (op, len), op in "MID"
     ref_packed: bool = False
+    h0: np.ndarray | None = None  # extension pairs: score of the anchor (int32 per pair)
 
     @property
     def n_pairs(self):
@@ -68,7 +69,8 @@ class Batch:
             read_len=self.read_len[idx], mode=self.mode[idx],
             planted_start=None if self.planted_start is None else self.planted_start[idx],
             planted_end=None if self.planted_end is None else self.planted_end[idx],
-            planted_ops=None if self.planted_ops is None else [self.planted_ops[i] for i in idx])
+            planted_ops=None if self.planted_ops is None else [self.planted_ops[i] for i in idx],
+            h0=None if self.h0 is None else self.h0[idx])
 
     def window_codes(self, p):
         o, n = int(self.win_off[p]), int(self.win_len[p])
@@ -362,6 +364,34 @@ def tiny_random(n_pairs, m_max, n_max, seed, mode=None, related=0.5):
     else:
         md = np.full(n_pairs, mode, np.uint8)
     return _finish("tiny", ref, win_off, n, codes, m, md)
+
+
+def extension_like(n_pairs, seed=0, m_max=150, band=32, ref_len=4_000_000, p_junk=0.2):
+    """Seed-extension pairs: the part of a read beyond an exact seed hit
+    against the reference that follows the hit.
+
+    Tail length m ~ U{0..m_max}; window = the m + band reference bases after
+    the hit; the tail is copied from the window start with 1% substitutions
+    and 0.3% indels (Geometric(1/2) lengths); a seeded fraction p_junk of
+    tails turn into uniform random bases from a point U{0..m-1} on (adapter
+    or chimeric ends, where clipping decides).  Anchor score h0 ~ U{19..60}
+    (the score of an exact seed of that many bases at match score 1).
+    Every pair has mode 2."""
+    rng = rng_for(11, seed)
+    m = rng.integers(0, m_max + 1, n_pairs).astype(np.int32)
+    n = (m + band).astype(np.int32)
+    ref = random_ref(rng, ref_len)
+    win_off = rng.integers(0, ref_len - int(n.max()) + 1, n_pairs).astype(np.int64)
+    codes, s, e, _ = _draw_reads(rng, lambda pos: ref[pos], win_off, win_off, m,
+                                 lambda idx: win_off[idx] + n[idx], 0.01, 0.003, "geom", False)
+    junk = (rng.random(n_pairs) < p_junk) & (m > 0)
+    for k in np.nonzero(junk)[0]:
+        c = int(rng.integers(0, m[k]))
+        codes[k, c:m[k]] = rng.integers(0, 4, int(m[k]) - c, dtype=np.uint8)
+    b = _finish("ext", ref, win_off, n, codes, m, np.full(n_pairs, 2))
+    b.h0 = rng.integers(19, 61, n_pairs).astype(np.int32)
+    b.junk = junk
+    return b
 
 
 def serving_like(n_pairs, ref_len=4_000_000, seed=0):

@@ -6,10 +6,13 @@ KEYS_END = ("score", "read_end", "ref_end")
 
 
 def run_gpu(ctx, batch, scoring=(1, -4, 6, 1), trace=True, cap=64, force_int32=False, plain=False,
-            max_read_len=None, max_win_len=None, mode="batch"):
+            max_read_len=None, max_win_len=None, mode="batch", h0="batch", default_h0=0, clip=0):
     import torch
     import paper_1402_4876_amd as mica
     dev = mica.to_device(batch)
+    if isinstance(h0, str):
+        h0 = batch.h0
+    h0_dev = None if h0 is None else torch.as_tensor(np.asarray(h0, np.int32)).cuda()
     md = dev["mode"] if mode == "batch" else None
     # every output starts as a sentinel, so a pair the kernels skip cannot
     # pass on values left in reused device memory
@@ -22,16 +25,21 @@ def run_gpu(ctx, batch, scoring=(1, -4, 6, 1), trace=True, cap=64, force_int32=F
                      dev["read_len"], mode=md, scoring=scoring, out_cigar=trace, cigar_cap=cap,
                      force_int32=force_int32, plain=plain, ref_len=dev["ref_len"], reads_len=dev["reads_len"],
                      max_read_len=max_read_len, max_win_len=max_win_len,
-                     default_mode=int(batch.mode[0]) if mode != "batch" and batch.n_pairs else 0, out=sentinel)
+                     default_mode=int(batch.mode[0]) if mode != "batch" and batch.n_pairs else 0, out=sentinel,
+                     ext_h0=h0_dev, ext_default_h0=default_h0, ext_clip=clip)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def run_oracle(batch, scoring=(1, -4, 6, 1), trace=True, cap=64, idx=None):
+def run_oracle(batch, scoring=(1, -4, 6, 1), trace=True, cap=64, idx=None, h0="batch", default_h0=0, clip=0):
     import oracle
     b = batch if idx is None else batch.subset(idx)
+    if isinstance(h0, str):
+        h0 = b.h0
+    elif h0 is not None and idx is not None:
+        h0 = np.asarray(h0)[idx]
     return oracle.align_batch(b.ref, b.win_off, b.win_len, b.reads, b.read_off, b.read_len, b.mode, scoring,
-                              trace=trace, cigar_cap=cap)
+                              trace=trace, cigar_cap=cap, h0=h0, default_h0=default_h0, clip=clip)
 
 
 def assert_same(g, o, trace=True, cap=64, idx=None, score_scale=1, what=""):

@@ -180,7 +180,7 @@ def test_pair_status_codes(ctx):
     win_off[3] = dev["ref_len"] - 2           # window past the end of the reference
     read_off[5] = dev["reads_len"] + 100      # read outside the read buffer
     read_len[7] = 31                          # above max_read_len (30)
-    mode[9] = 2                               # not a mode
+    mode[9] = 3                               # not a mode
     out = mica.align(ctx, dev["ref2b"], win_off, dev["win_len"], dev["reads2b"], read_off, read_len,
                      mode=mode, out_cigar=True, ref_len=dev["ref_len"], reads_len=dev["reads_len"],
                      max_read_len=30, max_win_len=40)
