@@ -54,24 +54,30 @@ __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
 constexpr int kPersistSmallMax = 9;
 constexpr int kPersistMaxClass = MICA_PERSIST_MAX_CLASS;
 __host__ __device__ constexpr bool persistent_bucket(int b) {
-  return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16 && bucket_class(b) <= kPersistMaxClass &&
-         bucket_mode(b) < 2;
+  return bucket_kind(b) == kK16 && class_lanes(bucket_class(b)) == 16 && bucket_class(b) <= kPersistMaxClass;
 }
 __host__ __device__ constexpr int persist_part(int cls) { return cls <= kPersistSmallMax ? 0 : 1; }
 // queue part of a persistent (mode, part): the long-read part of a mode
 // first (its items cost most), then the short-read part
 __host__ __device__ constexpr int persist_queue_part(int mode, int part) { return mode * 2 + (part ? 0 : 1); }
-constexpr int kQueueParts = 5;  // four persistent parts, then everything else
+constexpr int kPersistParts = 2 * kNumModes;
+constexpr int kQueueParts = kPersistParts + 1;  // the persistent parts, then everything else
 // the ordering key of buckets in the work queue
 __host__ __device__ constexpr int queue_part(int b) {
-  return persistent_bucket(b) ? persist_queue_part(bucket_mode(b), persist_part(bucket_class(b))) : 4;
+  return persistent_bucket(b) ? persist_queue_part(bucket_mode(b), persist_part(bucket_class(b))) : kPersistParts;
 }
 
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
 // counters[] slots
-// (queue heads of the four persistent kernels: kCtrQueueHead + queue part)
-enum : int { kCtrQueueHead = 0, kCtrRerun = 4, kCtrItems = 5, kCtrRerunHead = 6, kNumCounters = 8 };
+// (queue heads of the persistent kernels: kCtrQueueHead + queue part)
+enum : int {
+  kCtrQueueHead = 0,
+  kCtrRerun = kPersistParts,
+  kCtrItems,
+  kCtrRerunHead,
+  kNumCounters
+};
 
 // per-pair status bits (same values as the public header)
 constexpr uint32_t kStSaturated = 1u << 0;
@@ -149,7 +155,7 @@ typedef void (*KernelFn)(const Params*);
 // Kernel entry points of the library, indexed for the host runtime.
 struct KernelTable {
   KernelFn bucket[2][kNumBuckets];  // [with traceback][bucket]
-  KernelFn persistent[2][2][2];  // [with traceback][mode][class part]
+  KernelFn persistent[2][kNumModes][2];  // [with traceback][mode][class part]
   KernelFn rerun[2];
   KernelFn zero, plan, scan, scatter;
   KernelTable();

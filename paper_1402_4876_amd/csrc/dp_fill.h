@@ -914,7 +914,10 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, DIR)) void 
   const uint32_t items = (cnt + ppi - 1) / ppi;
   const uint32_t* base = prm->sorted + G(prm->bstart)[bucket];
   // waves take the bucket's items from a queue head (items differ in cost:
-  // window lengths and traceback paths vary)
+  // window lengths and traceback paths vary).  Any number of waves drains
+  // the queue, so waves beyond the item count leave at once rather than
+  // contend for the head (an empty bucket then costs its launch only).
+  if ((uint32_t)slot_id >= items) return;
   for (;;) {
     uint32_t v = 0;
     if ((threadIdx.x & 63) == 0) v = atomicAdd(&prm->bhead[bucket], 1u);

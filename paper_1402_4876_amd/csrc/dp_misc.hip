@@ -137,7 +137,7 @@ __global__ void k_scan(const Params* __restrict__ prm) {
   }
   prm->qstart[kNumBuckets] = items;
   prm->counters[kCtrItems] = items;
-  for (int q = 0; q < 4; ++q) prm->counters[kCtrQueueHead + q] = 0;
+  for (int q = 0; q < kPersistParts; ++q) prm->counters[kCtrQueueHead + q] = 0;
   prm->counters[kCtrRerun] = 0;
 }
 
@@ -185,7 +185,9 @@ namespace mica {
   X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1) \
   X(k16, 2, 0) X(k16, 2, 1) X(k16s, 2, 0) X(k16s, 2, 1) X(k32, 2, 0) X(k32, 2, 1)
 MICA_FILL_ALL(MICA_FILL_DECL)
-#define MICA_PERSIST_ALL(X) X(0, 0, 0) X(0, 0, 1) X(0, 1, 0) X(0, 1, 1) X(1, 0, 0) X(1, 0, 1) X(1, 1, 0) X(1, 1, 1)
+#define MICA_PERSIST_ALL(X) \
+  X(0, 0, 0) X(0, 0, 1) X(0, 1, 0) X(0, 1, 1) X(0, 2, 0) X(0, 2, 1) \
+  X(1, 0, 0) X(1, 0, 1) X(1, 1, 0) X(1, 1, 1) X(1, 2, 0) X(1, 2, 1)
 #define MICA_PERSIST_DECL(dir, mode, part) void reg_persistent_##dir##_##mode##_##part(KernelTable& t);
 MICA_PERSIST_ALL(MICA_PERSIST_DECL)
 

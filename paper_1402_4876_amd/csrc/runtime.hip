@@ -351,7 +351,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     bool part_used[2] = {false, false};
     for (int cls = 0; cls <= kPersistMaxClass; ++cls)
       if (cls_used[cls] && class_lanes(cls) == 16) part_used[persist_part(cls)] = true;
-    for (int md = 0; md < 2; ++md) {
+    for (int md = 0; md < kNumModes; ++md) {
       if (!any_mode[md]) continue;
       for (int part : {1, 0})
         if (part_used[part]) fills.push_back(K.persistent[d][md][part]);
