@@ -641,11 +641,18 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   lds_wait();
   if constexpr (DIR) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
 
-  // ---- outputs and traceback: lane k = h of each group handles pair h --------
-  if (k < NP && g * NP + k < npairs) {
+  // ---- outputs and traceback ---------------------------------------------------
+  // The X = P / NP lanes h*X .. h*X + X - 1 of a group serve its pair h.  In
+  // the walk, lane x of them examines the x-th cell ahead, so one iteration
+  // consumes up to X cells of a run of diagonal, deletion or insertion moves
+  // (a ballot finds where the run stops).  The walk's state is the same in
+  // all X lanes; lane x = 0 writes the outputs.
+  constexpr int X = P / NP;
+  const int h = k / X;
+  const int x = k - h * X;
+  if (g * NP + h < npairs) {
     // the pair's parameters are read again here rather than kept in
     // registers across the fill loop
-    const int h = k;
     const int p_ = (int)gpairs[g * NP + h];
     const int m_ = G(prm->read_len)[p_];
     const int n_ = G(prm->win_len)[p_];
@@ -655,160 +662,192 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     bool sat_;
     if constexpr (NP == 2) sat_ = h ? sat_h[1] : sat_h[0];
     else sat_ = sat_h[0];
-    {
-      if (sat_) {
+    if (sat_) {
+      if (x == 0) {
         const uint32_t pos = atomicAdd(&prm->counters[kCtrRerun], 1u);
         G(prm->rerun)[pos] = (uint32_t)p_;
-      } else {
-        const int score = (int)red[(g * NP + h) * 4 + 0] + d0_;
-        const int ie = (int)red[(g * NP + h) * 4 + 1];
-        const int je = (int)red[(g * NP + h) * 4 + 2];
+      }
+    } else {
+      const int score = (int)red[(g * NP + h) * 4 + 0] + d0_;
+      const int ie = (int)red[(g * NP + h) * 4 + 1];
+      const int je = (int)red[(g * NP + h) * 4 + 2];
+      if (x == 0) {
         G(prm->score)[p_] = score;
         G(prm->read_end)[p_] = ie;
         G(prm->ref_end)[p_] = je;
-        uint32_t st = 0;
-        if constexpr (DIR) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-          MICA_GLOBAL uint32_t* stg = (MICA_GLOBAL uint32_t*)(slot + prm->dir_bytes) +
-                                      (size_t)(g * NP + h) * (size_t)prm->stage_stride;
-          int i = ie, j = je;
-          int hval = score;  // true H of the current cell (local zero test)
-          int state = 0;     // 0: H, 1: D, 2: I
-          int nruns = 0, cur_op = -1, cur_len = 0;
-          // The walk only visits cells 1 <= i <= m, 1 <= j <= n, each step
-          // lowers i or j, so it emits at most ie + je ops.  A cell outside the
-          // matrix can only come from inconsistent direction bits: the walk
-          // then stops and the pair is flagged instead of reading out of range.
-          bool bad = ie < 0 || ie > m_ || je < 0 || je > n_;
-          // The walk reads direction words through a window of WW steps of
-          // one lane in LDS (the ring area, free after the fill): a path
-          // spends about R steps in a lane, so most lanes take one burst.
-          constexpr int WW = NP == 1 ? 4 : (NW == 4 ? (SAT ? 6 : 8) : (R + 3 < 8 ? R + 3 : 8));
-          static_assert(NP * WW * NW <= kRing, "walk windows exceed the group's ring");
-          uint32_t* win = ring + h * (WW * NW);
-          int win_k = -1, win_top = -1;
-          // local mode: the read and window words of the current bases
-          uint64_t q_idx = ~0ull, r_idx = ~0ull;
-          uint32_t q_word = 0, r_word = 0;
-          auto emit = [&](int op, int len) {
-            if (op == cur_op) {
-              cur_len += len;
-            } else {
-              if (cur_len > 0) stg[nruns++] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
-              cur_op = op;
-              cur_len = len;
+      }
+      uint32_t st = 0;
+      if constexpr (DIR) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        MICA_GLOBAL uint32_t* stg = (MICA_GLOBAL uint32_t*)(slot + prm->dir_bytes) +
+                                    (size_t)(g * NP + h) * (size_t)prm->stage_stride;
+        const MICA_GLOBAL uint32_t* dirw = (const MICA_GLOBAL uint32_t*)slot;  // NW words per (step, lane)
+        int i = ie, j = je;
+        int hval = score;  // true H of the current cell (local zero test)
+        int state = 0;     // 0: H, 1: D, 2: I
+        int nruns = 0, cur_op = -1, cur_len = 0;
+        // The walk only consumes cells 1 <= i <= m, 1 <= j <= n and lowers i
+        // or j with every cell, so it emits at most ie + je ops.  A cell
+        // outside the matrix can only come from inconsistent direction bits:
+        // the walk then stops and the pair is flagged instead of reading out
+        // of range.
+        bool bad = ie < 0 || ie > m_ || je < 0 || je > n_;
+        const int lane0 = lane - x;
+        constexpr uint64_t xmask = X == 64 ? ~0ull : ((1ull << (X == 64 ? 0 : X)) - 1);
+        auto sub = [&](bool pr) -> uint64_t { return (__ballot(pr) >> lane0) & xmask; };
+        // index of the first clear bit of a sub-group mask (X when all are set)
+        auto first_clear = [&](uint64_t msk) -> int {
+          const uint64_t z = ~msk & xmask;
+          return z ? (int)__builtin_ctzll(z) : X;
+        };
+        // direction word `which` (0: kinds 0 and 1, 1: kinds 2 and 3) of cell
+        // (ii, jj), taken from step offset dt; *bit receives the bit of kinds 0
+        // and 2 (kinds 1 and 3 sit 16 bits higher)
+        auto dir_word = [&](int ii, int jj, int dt, int which, int* bit) -> uint32_t {
+          const int u = d0_ + ii - 1;
+          const int kk = u / R;
+          const int rr = u - kk * R;
+          const int ts = jj + kk - 1 + dt;
+          *bit = 8 * h + (rr & 7);
+          const int wsel = (NW == 4 && rr >= 8 ? 2 : 0) + which;
+          return dirw[((size_t)ts * 64 + (size_t)(g * P + kk)) * NW + (size_t)wsel];
+        };
+        auto emit = [&](int op, int len) {
+          if (op == cur_op) {
+            cur_len += len;
+          } else {
+            if (cur_len > 0) {
+              if (x == 0) stg[nruns] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
+              ++nruns;
             }
-          };
-          while (!bad) {
-            if (state == 0) {
-              if (LOCAL && hval == 0) break;
-              if (i == 0) {
-                if (EXT && j > 0) {  // an extension starts at the anchor: a leading deletion
-                  emit(2, j);
-                  j = 0;
-                }
-                break;
+            cur_op = op;
+            cur_len = len;
+          }
+        };
+        while (!bad) {
+          if (state == 0) {
+            if (LOCAL && hval == 0) break;
+            if (i == 0) {
+              if (EXT && j > 0) {  // an extension starts at the anchor: a leading deletion
+                emit(2, j);
+                j = 0;
               }
-              if (!LOCAL && j == 0) {  // a leading insertion (semi-global, extension)
-                emit(1, i);
-                i = 0;
-                break;
-              }
+              break;
+            }
+            if (!LOCAL && j == 0) {  // a leading insertion (semi-global, extension)
+              emit(1, i);
+              i = 0;
+              break;
             }
             if (i < 1 || j < 1 || i > m_ || j > n_) {
               bad = true;
               break;
             }
-            const int u = d0_ + i - 1;
-            const int kk = u / R;
-            const int rr = u - kk * R;
-            // in a deletion the extend bit of (i, j) was stored with column
-            // j - 1; at j = 1 the deletion can only be opened (D(i,0) = -inf)
-            const int ts = j + kk - 1 - (state == 1 ? 1 : 0);
-            uint32_t w01 = 0, w23 = 0;
-            if (state != 1 || j > 1) {
-              if (kk != win_k || ts > win_top || ts <= win_top - WW) {
-                // steps ts, ts-1, ... of lane kk in one burst of independent
-                // loads (clamped at step kk, the lane's first real column),
-                // then into the walker's LDS window
-                win_k = kk;
-                win_top = ts;
-                const int base = g * P + kk;
-                if constexpr (NW == 4) {
-                  u32x4 tmp[WW];
-#pragma unroll
-                  for (int x = 0; x < WW; ++x) tmp[x] = dir4[(ts - x >= kk ? ts - x : kk) * 64 + base];
-#pragma unroll
-                  for (int x = 0; x < WW; ++x) *(u32x4*)(win + 4 * x) = tmp[x];
-                } else {
-                  u32x2 tmp[WW];
-#pragma unroll
-                  for (int x = 0; x < WW; ++x) tmp[x] = dir2[(ts - x >= kk ? ts - x : kk) * 64 + base];
-#pragma unroll
-                  for (int x = 0; x < WW; ++x) *(u32x2*)(win + 2 * x) = tmp[x];
-                }
-              }
-              if constexpr (NW == 4) {
-                const u32x4 w = *(const u32x4*)(win + 4 * (win_top - ts));
-                w01 = rr >= 8 ? w.z : w.x;
-                w23 = rr >= 8 ? w.w : w.y;
-              } else {
-                const u32x2 w = *(const u32x2*)(win + 2 * (win_top - ts));
-                w01 = w.x;
-                w23 = w.y;
+            // lane x: the diagonal cell (i - x, j - x)
+            const int ic = i - x, jc = j - x;
+            const bool in = ic >= 1 && jc >= 1;
+            bool diag = false, dlose = false;
+            int sc = 0;
+            if (in) {
+              int bit;
+              const uint32_t w = dir_word(ic, jc, 0, 0, &bit);
+              diag = ((w >> bit) & 1u) == 0;
+              dlose = ((w >> (bit + 16)) & 1u) != 0;
+              if constexpr (LOCAL) {
+                const uint64_t qp = ro_ + (uint64_t)(ic - 1), rp = wo_ + (uint64_t)(jc - 1);
+                const uint32_t qb = (reads2b[qp >> 4] >> (2 * (uint32_t)(qp & 15))) & 3u;
+                const uint32_t rb = (ref2b[rp >> 4] >> (2 * (uint32_t)(rp & 15))) & 3u;
+                sc = qb == rb ? sa : sb;
               }
             }
-            const int bit = 8 * h + (rr & 7);  // kinds 0 and 2 at bit, 1 and 3 at bit + 16
-            if (state == 0) {
-              if (((w01 >> bit) & 1u) == 0) {
-                emit(0, 1);
-                if (LOCAL) {
-                  const uint64_t qp = ro_ + (uint64_t)(i - 1), rp = wo_ + (uint64_t)(j - 1);
-                  if ((qp >> 4) != q_idx) {
-                    q_idx = qp >> 4;
-                    q_word = reads2b[q_idx];
-                  }
-                  if ((rp >> 4) != r_idx) {
-                    r_idx = rp >> 4;
-                    r_word = ref2b[r_idx];
-                  }
-                  const uint32_t qb = (q_word >> (2 * (uint32_t)(qp & 15))) & 3u;
-                  const uint32_t rb = (r_word >> (2 * (uint32_t)(rp & 15))) & 3u;
-                  hval -= (qb == rb) ? sa : sb;
-                }
-                --i;
-                --j;
-              } else if (((w01 >> (bit + 16)) & 1u) == 0) {
-                state = 1;
-              } else {
-                state = 2;
+            // local: the H of cell x is hval less the scores of cells 0..x-1,
+            // and the walk stops before a cell whose H is 0
+            int incl = sc;
+            if constexpr (LOCAL) {
+#pragma unroll
+              for (int d = 1; d < X; d *= 2) {
+                const int t = __shfl_up(incl, d, X);
+                if (x >= d) incl += t;
               }
-            } else if (state == 1) {
-              emit(2, 1);
-              if ((w23 >> bit) & 1u) {
-                hval += se;
-              } else {
-                hval += oe;
-                state = 0;
-              }
-              --j;
+            }
+            const bool zero = LOCAL && hval - (incl - sc) == 0;
+            const int L = first_clear(sub(in && diag && !zero));
+            const uint64_t turn = sub(in && !diag && !zero);
+            const uint64_t dl = sub(dlose);
+            if (L > 0) {
+              emit(0, L);
+              if constexpr (LOCAL) hval -= __shfl(incl, L - 1, X);
+              i -= L;
+              j -= L;
+            }
+            // a cell that turns into a gap sets the state here; boundaries,
+            // range and the zero stop are left to the next iteration
+            if (L < X && ((turn >> L) & 1u)) state = ((dl >> L) & 1u) ? 2 : 1;
+            continue;
+          }
+          if (i < 1 || j < 1 || i > m_ || j > n_) {
+            bad = true;
+            break;
+          }
+          if (state == 1) {
+            // a deletion along row i: the extend bit of (i, j - x) was stored
+            // with column j - x - 1; at column 1 a deletion can only open
+            const int jc = j - x;
+            bool ext = false;
+            if (jc >= 2) {
+              int bit;
+              const uint32_t w = dir_word(i, jc, -1, 1, &bit);
+              ext = ((w >> bit) & 1u) != 0;
+            }
+            const int ones = first_clear(sub(ext));
+            if (ones < X) {  // cells 0..ones-1 extend, cell `ones` opens
+              const int L = ones + 1;
+              emit(2, L);
+              hval += oe + (L - 1) * se;
+              j -= L;
+              state = 0;
             } else {
-              emit(1, 1);
-              if ((w23 >> (bit + 16)) & 1u) {
-                hval += se;
-              } else {
-                hval += oe;
-                state = 0;
-              }
-              --i;
+              emit(2, X);
+              hval += X * se;
+              j -= X;
+            }
+          } else {
+            // an insertion up column j: the extend bit of (i - x, j)
+            const int ic = i - x;
+            const bool in = ic >= 1;
+            bool ext = false;
+            if (in) {
+              int bit;
+              const uint32_t w = dir_word(ic, j, 0, 1, &bit);
+              ext = ((w >> (bit + 16)) & 1u) != 0;
+            }
+            const int ones = first_clear(sub(ext));
+            const uint64_t inm = sub(in);
+            if (ones < X && ((inm >> ones) & 1u)) {
+              const int L = ones + 1;
+              emit(1, L);
+              hval += oe + (L - 1) * se;
+              i -= L;
+              state = 0;
+            } else {
+              // X extensions, or a run that would leave the matrix (flagged
+              // by the range check of the next iteration)
+              emit(1, ones);
+              hval += ones * se;
+              i -= ones;
             }
           }
-          if (cur_len > 0) stg[nruns++] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
-          if (bad) {
-            st |= kStInternal;
-            i = j = 0;
-            nruns = 0;
-          }
+        }
+        if (cur_len > 0) {
+          if (x == 0) stg[nruns] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
+          ++nruns;
+        }
+        if (bad) {
+          st |= kStInternal;
+          i = j = 0;
+          nruns = 0;
+        }
+        if (x == 0) {
           if (prm->flags & (kOutStart | kOutCigar)) {
             G(prm->read_start)[p_] = i;
             G(prm->ref_start)[p_] = j;
@@ -817,7 +856,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             const int cap = prm->cigar_cap;
             MICA_GLOBAL uint32_t* out = G(prm->cigar) + (size_t)p_ * (size_t)cap;
             const int ncopy = nruns < cap ? nruns : cap;
-            for (int x = 0; x < ncopy; ++x) out[x] = stg[nruns - 1 - x];
+            for (int y = 0; y < ncopy; ++y) out[y] = stg[nruns - 1 - y];
             if (nruns > cap) {
               st |= kStCigarTrunc;
               G(prm->n_cigar)[p_] = -nruns;
@@ -826,8 +865,8 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
             }
           }
         }
-        G(prm->status)[p_] = st;
       }
+      if (x == 0) G(prm->status)[p_] = st;
     }
   }
   lds_wait();
@@ -877,6 +916,8 @@ k_fill_persistent(const Params* __restrict__ prm) {
   const int q0 = (int)prm->persist_q[QP], q1 = (int)prm->persist_q[QP + 1];
   const uint32_t base_item = G(prm->qstart)[q0];
   const uint32_t total = G(prm->qstart)[q1];
+  // waves beyond the part's item count leave at once (see k_fill_bucket)
+  if ((uint32_t)slot_id >= total - base_item) return;
   for (;;) {
     uint32_t v = 0;
     if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead + QP], 1u);

@@ -235,6 +235,7 @@ bool launch_slot(mica_server* s, Slot& sl) {
   b.read_len = (const int32_t*)(sl.d_in + L.read_len);
   b.mode = any_local ? (const uint8_t*)(sl.d_in + L.mode) : nullptr;
   b.default_mode = MICA_MODE_SEMIGLOBAL;
+  b.mode_mask = (1 << MICA_MODE_SEMIGLOBAL) | (1 << MICA_MODE_LOCAL);  // requests hold modes 0 and 1 only
   b.n_pairs = n;
   b.max_read_len = max_m;
   b.max_win_len = max_n;
