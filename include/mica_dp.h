@@ -88,7 +88,7 @@ enum {
 enum {
   MICA_ST_SATURATED = 1u << 0,   /* 16-bit scores saturated; the 32-bit re-run result is final */
   MICA_ST_CIGAR_TRUNC = 1u << 1, /* n_cigar = -(runs needed); cigar holds the first cigar_cap runs */
-  MICA_ST_LEN_LIMIT = 1u << 2,   /* m or n outside [0, max_*_len], mode not 0/1/2 (or outside mode_mask), or h0 out of range */
+  MICA_ST_LEN_LIMIT = 1u << 2,   /* m outside [min_read_len, max_read_len], n outside [0, max_win_len], mode not 0/1/2 (or outside mode_mask), or h0 out of range */
   MICA_ST_WIN_OOB = 1u << 3,     /* window not inside the reference: not computed */
   MICA_ST_READ_OOB = 1u << 4,    /* read not inside the read buffer: not computed */
   MICA_ST_INTERNAL = 1u << 5     /* a device consistency check failed; coordinates and CIGAR invalid */
@@ -150,6 +150,11 @@ typedef struct {
    * launched; a pair whose mode is outside the mask gets MICA_ST_LEN_LIMIT.
    * Ignored without a mode array. */
   int32_t mode_mask;
+  /* host-side lower bound of read_len over the batch (0 = none).  With the
+   * upper bound it tells which read-length classes the batch can hold; a
+   * batch of one class runs it as a plain launch.  A pair below it gets
+   * MICA_ST_LEN_LIMIT. */
+  int32_t min_read_len;
 } mica_batch_t;
 
 /* Align every pair of `batch` (Methods, DP section; readings above).

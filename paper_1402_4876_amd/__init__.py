@@ -129,7 +129,8 @@ def pack_2bit(codes, stream=None):
 
 def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring, out_start, out_cigar,
                 cigar_cap, force_int32, plain, graph, default_mode, max_read_len, max_win_len, ref_len,
-                reads_len, out, outputs=True, ext_h0=None, ext_default_h0=0, ext_clip=0, mode_mask=0):
+                reads_len, out, outputs=True, ext_h0=None, ext_default_h0=0, ext_clip=0, mode_mask=0,
+                min_read_len=0):
     ref2b = _dev(ref2b, torch.int32, "ref2b")
     reads2b = _dev(reads2b, torch.int32, "reads2b")
     win_off = _dev(win_off, torch.int64, "win_off")
@@ -194,6 +195,7 @@ def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scor
     b.ext_default_h0 = int(ext_default_h0)
     b.ext_clip = int(ext_clip)
     b.mode_mask = int(mode_mask)
+    b.min_read_len = int(min_read_len)
     a_, b_, o_, e_ = (int(x) for x in scoring)
     sc = _lib.Scoring(a_, b_, o_, e_)
     flags = (OUT_START if out_start else 0) | (OUT_CIGAR if out_cigar else 0) | \
@@ -205,7 +207,7 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
           out_start=False, out_cigar=False, cigar_cap=64, force_int32=False, plain=False, graph=True,
           default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
           reads_len=None, out=None, stream=None, ext_h0=None, ext_default_h0=0, ext_clip=0,
-          mode_mask=0):
+          mode_mask=0, min_read_len=0):
     """Align every (read, window) pair on the GPU; returns a dict of tensors.
 
     ref2b / reads2b: int32 tensors of 2-bit packed bases; win_off / read_off:
@@ -218,13 +220,16 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
     ``ext_h0`` (int32 per pair) or ``ext_default_h0`` and are clipped unless
     the whole read scores within ``ext_clip`` of the best early end.
     ``mode_mask`` (bit per mode, 0 = all) names the modes a ``mode`` array
-    may hold, so kernels of absent modes are not launched.  The
+    may hold, so kernels of absent modes are not launched; ``min_read_len``
+    (with ``max_read_len``) bounds the read lengths, so a batch of one
+    length class runs that class's own kernel.  The
     call is asynchronous on ``stream``.
     """
     b, sc, flags, out = _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring,
                                     out_start, out_cigar, cigar_cap, force_int32, plain, graph, default_mode,
                                     max_read_len, max_win_len, ref_len, reads_len, out, ext_h0=ext_h0,
-                                    ext_default_h0=ext_default_h0, ext_clip=ext_clip, mode_mask=mode_mask)
+                                    ext_default_h0=ext_default_h0, ext_clip=ext_clip, mode_mask=mode_mask,
+                                    min_read_len=min_read_len)
     _lib.check(_lib.load().mica_dp_align_batch(ctx.handle, ctypes.byref(b), ctypes.byref(sc), flags,
                                                _stream_handle(stream)))
     return out

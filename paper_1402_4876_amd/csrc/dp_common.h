@@ -112,6 +112,7 @@ struct Params {
   const uint8_t* mode;
   int32_t default_mode;
   int32_t max_m, max_n;
+  int32_t min_m;  // pairs with fewer read bases are rejected (a launch-planning bound)
   int64_t n_pairs;
   int32_t* score;
   int32_t* read_end;

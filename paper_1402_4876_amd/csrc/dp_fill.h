@@ -643,9 +643,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 
   // ---- outputs and traceback ---------------------------------------------------
   // The X = P / NP lanes h*X .. h*X + X - 1 of a group serve its pair h.  In
-  // the walk, lane x of them examines the x-th cell ahead, so one iteration
-  // consumes up to X cells of a run of diagonal, deletion or insertion moves
-  // (a ballot finds where the run stops).  The walk's state is the same in
+  // the walk, lane x of them examines cells x, x + X, ... ahead, so one
+  // iteration consumes a run of diagonal moves of up to 64 cells, or of
+  // deletion or insertion moves of up to X cells (a ballot finds where the
+  // run stops).  The walk's state is the same in
   // all X lanes; lane x = 0 writes the outputs.
   constexpr int X = P / NP;
   const int h = k / X;
@@ -700,6 +701,17 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
           const uint64_t z = ~msk & xmask;
           return z ? (int)__builtin_ctzll(z) : X;
         };
+        // a diagonal run is examined C cells per lane, X*C <= 64 at a time
+        // (measured: 64 cells pay off on the long diagonals of semi-global
+        // reads; local and extension walks, with more turns, do as well with
+        // 32 or fewer)
+        constexpr int C = MODE == 0 ? 64 / X : (X <= 16 ? 4 : (X == 32 ? 2 : 1));
+        constexpr int XC = X * C;
+        constexpr uint64_t xcmask = XC == 64 ? ~0ull : ((1ull << (XC == 64 ? 0 : XC)) - 1);
+        auto first_clear_xc = [&](uint64_t msk) -> int {
+          const uint64_t z = ~msk & xcmask;
+          return z ? (int)__builtin_ctzll(z) : XC;
+        };
         // direction word `which` (0: kinds 0 and 1, 1: kinds 2 and 3) of cell
         // (ii, jj), taken from step offset dt; *bit receives the bit of kinds 0
         // and 2 (kinds 1 and 3 sit 16 bits higher)
@@ -743,46 +755,70 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
               bad = true;
               break;
             }
-            // lane x: the diagonal cell (i - x, j - x)
-            const int ic = i - x, jc = j - x;
-            const bool in = ic >= 1 && jc >= 1;
-            bool diag = false, dlose = false;
-            int sc = 0;
-            if (in) {
-              int bit;
-              const uint32_t w = dir_word(ic, jc, 0, 0, &bit);
-              diag = ((w >> bit) & 1u) == 0;
-              dlose = ((w >> (bit + 16)) & 1u) != 0;
-              if constexpr (LOCAL) {
-                const uint64_t qp = ro_ + (uint64_t)(ic - 1), rp = wo_ + (uint64_t)(jc - 1);
-                const uint32_t qb = (reads2b[qp >> 4] >> (2 * (uint32_t)(qp & 15))) & 3u;
-                const uint32_t rb = (ref2b[rp >> 4] >> (2 * (uint32_t)(rp & 15))) & 3u;
-                sc = qb == rb ? sa : sb;
-              }
-            }
-            // local: the H of cell x is hval less the scores of cells 0..x-1,
-            // and the walk stops before a cell whose H is 0
-            int incl = sc;
-            if constexpr (LOCAL) {
+            // lane x: the diagonal cells c = x + X*cc, cc < C, that is
+            // (i - c, j - c); all their loads are in flight at once
+            bool in[C], diag[C], dlose[C];
+            int sc[C], incl[C];
 #pragma unroll
-              for (int d = 1; d < X; d *= 2) {
-                const int t = __shfl_up(incl, d, X);
-                if (x >= d) incl += t;
+            for (int cc = 0; cc < C; ++cc) {
+              const int c = x + X * cc;
+              const int ic = i - c, jc = j - c;
+              in[cc] = ic >= 1 && jc >= 1;
+              diag[cc] = false;
+              dlose[cc] = false;
+              sc[cc] = 0;
+              if (in[cc]) {
+                int bit;
+                const uint32_t w = dir_word(ic, jc, 0, 0, &bit);
+                diag[cc] = ((w >> bit) & 1u) == 0;
+                dlose[cc] = ((w >> (bit + 16)) & 1u) != 0;
+                if constexpr (LOCAL) {
+                  const uint64_t qp = ro_ + (uint64_t)(ic - 1), rp = wo_ + (uint64_t)(jc - 1);
+                  const uint32_t qb = (reads2b[qp >> 4] >> (2 * (uint32_t)(qp & 15))) & 3u;
+                  const uint32_t rb = (ref2b[rp >> 4] >> (2 * (uint32_t)(rp & 15))) & 3u;
+                  sc[cc] = qb == rb ? sa : sb;
+                }
               }
             }
-            const bool zero = LOCAL && hval - (incl - sc) == 0;
-            const int L = first_clear(sub(in && diag && !zero));
-            const uint64_t turn = sub(in && !diag && !zero);
-            const uint64_t dl = sub(dlose);
+            // local: the H of cell c is hval less the scores of cells 0..c-1
+            // (incl[cc]: the scores of cells 0..c), and the walk stops before
+            // a cell whose H is 0
+#pragma unroll
+            for (int cc = 0; cc < C; ++cc) {
+              incl[cc] = sc[cc];
+              if constexpr (LOCAL) {
+#pragma unroll
+                for (int d = 1; d < X; d *= 2) {
+                  const int t = __shfl_up(incl[cc], d, X);
+                  if (x >= d) incl[cc] += t;
+                }
+                if (cc > 0) incl[cc] += __shfl(incl[cc - 1], X - 1, X);
+              }
+            }
+            uint64_t good = 0, turn = 0, dl = 0;
+#pragma unroll
+            for (int cc = 0; cc < C; ++cc) {
+              const bool zero = LOCAL && hval - (incl[cc] - sc[cc]) == 0;
+              good |= sub(in[cc] && diag[cc] && !zero) << (X * cc);
+              turn |= sub(in[cc] && !diag[cc] && !zero) << (X * cc);
+              dl |= sub(dlose[cc]) << (X * cc);
+            }
+            const int L = first_clear_xc(good);
             if (L > 0) {
               emit(0, L);
-              if constexpr (LOCAL) hval -= __shfl(incl, L - 1, X);
+              if constexpr (LOCAL) {
+                int used = 0;
+#pragma unroll
+                for (int cc = 0; cc < C; ++cc)
+                  if ((L - 1) / X == cc) used = __shfl(incl[cc], (L - 1) % X, X);
+                hval -= used;
+              }
               i -= L;
               j -= L;
             }
             // a cell that turns into a gap sets the state here; boundaries,
             // range and the zero stop are left to the next iteration
-            if (L < X && ((turn >> L) & 1u)) state = ((dl >> L) & 1u) ? 2 : 1;
+            if (L < XC && ((turn >> L) & 1u)) state = ((dl >> L) & 1u) ? 2 : 1;
             continue;
           }
           if (i < 1 || j < 1 || i > m_ || j > n_) {

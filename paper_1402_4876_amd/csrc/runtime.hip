@@ -315,6 +315,8 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     return fail(MICA_ERR_INVALID_ARG, "extension start score or clipping penalty outside 0..2^20");
   if (b->max_read_len < 0 || b->max_read_len > kMaxM || b->max_win_len < 0 || b->max_win_len > kMaxN)
     return fail(MICA_ERR_LIMIT, "max_read_len / max_win_len beyond the library limits");
+  if (b->min_read_len < 0 || b->min_read_len > b->max_read_len)
+    return fail(MICA_ERR_INVALID_ARG, "min_read_len outside [0, max_read_len]");
   const bool want_cigar = flags & MICA_OUT_CIGAR;
   const bool want_start = want_cigar || (flags & MICA_OUT_START);
   if (b->n_pairs == 0) return MICA_OK;
@@ -344,9 +346,16 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   const bool may_sat = !forced && (any_ext || !int16_always_safe(max_m, max_n, *s, any_local, any_sg));
   const bool plain = flags & MICA_PLAIN_LAUNCH;
   bool cls_used[kNumClasses] = {};
-  for (int m = 1; m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
+  for (int m = std::max(1, b->min_read_len); m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
+  // a batch of one persistent class gains nothing from the persistent
+  // kernels (they balance classes against each other) and its plain kernel
+  // is compiled for that class alone
+  int n_persist_cls = 0;
+  for (int cls = 0; cls <= kPersistMaxClass; ++cls)
+    if (cls_used[cls] && class_lanes(cls) == 16) ++n_persist_cls;
+  const bool persist = !plain && !forced && n_persist_cls > 1;
   std::vector<KernelFn> fills;
-  if (!plain && !forced) {
+  if (persist) {
     // persistent parts in queue order: per mode, long reads first
     bool part_used[2] = {false, false};
     for (int cls = 0; cls <= kPersistMaxClass; ++cls)
@@ -367,7 +376,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
       for (int md = 0; md < kNumModes; ++md) {
         if (!any_mode[md]) continue;
         const int bk = bucket_id(kind, cls, md);
-        if (!plain && persistent_bucket(bk)) continue;
+        if (persist && persistent_bucket(bk)) continue;
         fills.push_back(K.bucket[d][bk]);
       }
     }
@@ -427,6 +436,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.ext_clip = b->ext_clip;
   P.mode_mask = mode_mask;
   P.max_m = max_m;
+  P.min_m = b->min_read_len;
   P.max_n = max_n;
   P.n_pairs = b->n_pairs;
   P.score = b->score;

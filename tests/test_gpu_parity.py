@@ -247,3 +247,23 @@ def test_config1_full_size_sampled(ctx, plain):
     ref_span = (L * ((op == 0) | (op == 2))).sum(axis=1)
     assert np.array_equal(read_span, g["read_end"] - g["read_start"])
     assert np.array_equal(ref_span, g["ref_end"] - g["ref_start"])
+
+
+def test_min_read_len_hint(ctx):
+    """A batch of one length class (bounded by min_read_len) runs its class
+    kernel instead of the persistent ones, with the same results; a pair
+    below the bound is rejected per pair."""
+    import paper_1402_4876_amd as mica
+    b = synth.config1(n_pairs=5000, ref_len=1_000_000)
+    o = U.run_oracle(b, SC)
+    g = U.run_gpu(ctx, b, SC, min_read_len=150)
+    U.assert_same(g, o, what="one class")
+    U.assert_equal_outputs(g, U.run_gpu(ctx, b, SC), "hinted vs not")
+    g2 = U.run_gpu(ctx, b, SC, min_read_len=150, max_read_len=150)
+    U.assert_same(g2, o, what="tight bounds")
+    mixed = synth.tiny_random(800, 60, 90, 21)
+    gm = U.run_gpu(ctx, mixed, SC, min_read_len=20)
+    low = mixed.read_len < 20
+    assert (gm["status"][low] == mica.ST_LEN_LIMIT).all()
+    keep = np.nonzero(~low)[0]
+    U.assert_same(gm, U.run_oracle(mixed, SC, idx=keep), idx=keep, what="above the bound")
