@@ -43,11 +43,11 @@ EXT_CLIP = 5  # clipping penalty of the seed-extension workload
 KERNEL_SOURCES = ("dp_fill.h", "dp_common.h")
 MEASURED_TRAFFIC = {
     # config: (kernel source sha256, fetch bytes, write bytes); for the
-    # extension workload the sums over its per-bucket fill launches and re-run
-    "c1": ("b89da4d23fcd4c11855b6a00d9e4bb235bd3d65497febe3d0fe7baf27eb68a19",
-           round(1.20021e7 * 2048), round(5.23481e7 * 1024)),
-    "ext": ("b89da4d23fcd4c11855b6a00d9e4bb235bd3d65497febe3d0fe7baf27eb68a19",
-            round(3.82670e6 * 2048), round(9.95028e6 * 1024)),
+    # extension workload the sums over its fill launches and re-run
+    "c1": ("fd16b224fc48516df4060b6014ae6c449a82486f725cbe56051584b507e56327",
+           round(9.89829e6 * 2048), round(5.19913e7 * 1024)),
+    "ext": ("fd16b224fc48516df4060b6014ae6c449a82486f725cbe56051584b507e56327",
+            round(4.13141e6 * 2048), round(1.00150e7 * 1024)),
 }
 
 
