@@ -1,13 +1,16 @@
-"""CPU oracle for affine-gap read alignment -- test infrastructure only.
+"""CPU oracle for affine-gap read alignment and few-mismatch search -- test
+infrastructure only.
 
 Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU library never calls it and
-shares no code with it.  ``gotoh.c`` holds the arithmetic (full int32 H, D
-and I matrices, best cell, traceback); this module only compiles it with
-gcc and marshals numpy arrays through ctypes.
+shares no code with it.  ``gotoh.c`` holds the DP arithmetic (full int32 H,
+D and I matrices, best cell, traceback); ``kmm.c`` the few-mismatch search
+as its definition (every placement of every read, brute force).  This
+module only compiles them with gcc and marshals numpy arrays through
+ctypes.
 
-Parity status: pinned (exhaustive enumeration, closed forms and invariants;
-see ``tests/test_oracle_*.py``).
+Parity status: pinned (exhaustive enumeration, closed forms, library
+routines and invariants; see ``tests/test_oracle_*.py``).
 """
 from __future__ import annotations
 
@@ -19,7 +22,7 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "gotoh.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("gotoh.c", "kmm.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -28,6 +31,7 @@ ST_CIGAR_TRUNC = 1 << 1
 ST_LEN_LIMIT = 1 << 2
 ST_WIN_OOB = 1 << 3
 ST_READ_OOB = 1 << 4
+ST_REPETITIVE = 1 << 6
 
 SEMIGLOBAL = 0
 LOCAL = 1
@@ -37,11 +41,11 @@ DEFAULT_SCORING = (1, -4, 6, 1)  # match, mismatch, gap open, gap extend
 
 
 def build(force: bool = False) -> str:
-    """Compile gotoh.c into liboracle.so with gcc -O2 (plain C, no intrinsics)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile gotoh.c and kmm.c into liboracle.so with gcc -O2 (plain C, no intrinsics)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp]
+            ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-pthread"] + _SRCS + ["-o", tmp]
         )
         os.replace(tmp, _LIB)
     return _LIB
@@ -65,6 +69,9 @@ def bind(lib):
         i32, i32, i32, i32, i32, i32,
         P, P, P, P, P, P, P, P, i32,
     ]
+    if hasattr(lib, "oracle_kmm_search"):
+        lib.oracle_kmm_search.restype = ctypes.c_int
+        lib.oracle_kmm_search.argtypes = [P, i64, P, i64, P, P, i64, i32, i32, P, P, P, P, P, i32]
     return lib
 
 
@@ -157,3 +164,33 @@ def align_pairs(pairs, mode=SEMIGLOBAL, scoring=DEFAULT_SCORING, trace=True, cig
 def decode_cigar(words, n):
     """CIGAR words -> string such as '4M1D4M' (test helper)."""
     return "".join("%d%s" % (int(w) >> 4, "MID"[int(w) & 15]) for w in words[:n])
+
+
+def kmm_search(ref, reads, read_off, read_len, k=2, max_occ=64, threads=None):
+    """Few-mismatch search by its definition: for every read, every position
+    p <= L - m whose placement has at most ``k`` mismatches.
+
+    ``ref`` and ``reads`` hold one base code per byte.  Returns a dict of
+    numpy arrays: best_mm (smallest mismatch count, -1 without hits),
+    n_best (hits with that count), n_hits (all hits), pos (leftmost hit with
+    the smallest count, -1 without) and status (ST_LEN_LIMIT, ST_READ_OOB,
+    ST_REPETITIVE when one of the k + 1 parts occurs more than ``max_occ``
+    times).
+    """
+    lib = _load()
+    ref = np.ascontiguousarray(ref, dtype=np.uint8)
+    reads = np.ascontiguousarray(reads, dtype=np.uint8)
+    read_off = np.ascontiguousarray(read_off, dtype=np.int64)
+    read_len = np.ascontiguousarray(read_len, dtype=np.int32)
+    n = len(read_off)
+    assert len(read_len) == n
+    out = {"best_mm": np.zeros(n, np.int32), "n_best": np.zeros(n, np.int32), "n_hits": np.zeros(n, np.int32),
+           "pos": np.zeros(n, np.int64), "status": np.zeros(n, np.uint32)}
+    if threads is None:
+        threads = os.cpu_count() or 1
+    rc = lib.oracle_kmm_search(_ptr(ref), len(ref), _ptr(reads), len(reads), _ptr(read_off), _ptr(read_len), n,
+                               int(k), int(max_occ), _ptr(out["best_mm"]), _ptr(out["n_best"]),
+                               _ptr(out["n_hits"]), _ptr(out["pos"]), _ptr(out["status"]), int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected k or max_occ")
+    return out
