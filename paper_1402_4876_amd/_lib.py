@@ -31,6 +31,7 @@ ST_LEN_LIMIT = 1 << 2
 ST_WIN_OOB = 1 << 3
 ST_READ_OOB = 1 << 4
 ST_INTERNAL = 1 << 5
+ST_REPETITIVE = 1 << 6
 
 MAX_READ_LEN = 1024
 MAX_WIN_LEN = 8192
@@ -39,7 +40,8 @@ EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_p
            "mica_ctx_set_plan", "mica_ctx_last_stats", "mica_ctx_set_timing", "mica_ctx_read_timing",
            "mica_ctx_autotune", "mica_ctx_save_plan", "mica_ctx_load_plan", "mica_server_create",
            "mica_server_now", "mica_server_submit", "mica_server_poll", "mica_server_fetch", "mica_server_stats",
-           "mica_server_reset_stats", "mica_server_destroy", "mica_last_error")
+           "mica_server_reset_stats", "mica_server_destroy", "mica_last_error", "mica_fm_suffix_array",
+           "mica_fm_create", "mica_fm_destroy", "mica_fm_info", "mica_fm_search")
 
 
 class Scoring(ctypes.Structure):
@@ -79,6 +81,16 @@ class TuneEntry(ctypes.Structure):
 
 
 _lib = None
+
+
+class FmBatch(ctypes.Structure):
+    """mica_fm_batch_t of include/mica_fm.h."""
+    _fields_ = [
+        ("reads2b", ctypes.c_void_p), ("reads_len", ctypes.c_uint64), ("read_off", ctypes.c_void_p),
+        ("read_len", ctypes.c_void_p), ("n_reads", ctypes.c_int64), ("k", ctypes.c_int32),
+        ("max_occ", ctypes.c_int32), ("best_mm", ctypes.c_void_p), ("n_best", ctypes.c_void_p),
+        ("n_hits", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("status", ctypes.c_void_p),
+    ]
 
 
 def load():
@@ -126,6 +138,13 @@ def load():
     lib.mica_server_destroy.argtypes = [P]
     for f in ("create", "now", "submit", "poll", "fetch", "stats", "reset_stats", "destroy"):
         getattr(lib, "mica_server_" + f).restype = ctypes.c_int
+    lib.mica_fm_suffix_array.argtypes = [P, ctypes.c_uint64, P]
+    lib.mica_fm_create.argtypes = [ctypes.c_int, P, ctypes.c_uint64, ctypes.POINTER(P)]
+    lib.mica_fm_destroy.argtypes = [P]
+    lib.mica_fm_info.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), D]
+    lib.mica_fm_search.argtypes = [P, ctypes.POINTER(FmBatch), P]
+    for f in ("suffix_array", "create", "destroy", "info", "search"):
+        getattr(lib, "mica_fm_" + f).restype = ctypes.c_int
     lib.mica_last_error.argtypes = []
     lib.mica_last_error.restype = ctypes.c_char_p
     _lib = lib

@@ -7,13 +7,16 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mica_dp.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mica_\w+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(mica_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -31,8 +34,9 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     from paper_1402_4876_amd import _lib
     structs = {"mica_batch_t": _lib.Batch, "mica_scoring_t": _lib.Scoring, "mica_batch_stats_t": _lib.BatchStats,
-               "mica_tune_entry_t": _lib.TuneEntry}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mica_dp.h"', 'int main(void) {']
+               "mica_tune_entry_t": _lib.TuneEntry, "mica_fm_batch_t": _lib.FmBatch}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mica_dp.h"', '#include "mica_fm.h"',
+             'int main(void) {']
     for cname, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
         for f, _ in cls._fields_:
@@ -98,3 +102,33 @@ def test_binding_refuses_missing_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_suffix_array_matches_sorting():
+    """The library's SA-IS against plain sorting of all suffixes (host only)."""
+    import paper_1402_4876_amd as mica
+    rng = np.random.default_rng(7)
+    cases = [np.zeros(0, np.uint8), np.zeros(1, np.uint8), np.zeros(50, np.uint8), np.full(33, 3, np.uint8),
+             np.tile(np.array([0, 1], np.uint8), 40), np.tile(np.array([2, 2, 1], np.uint8), 30),
+             np.tile(rng.integers(0, 4, 7, dtype=np.uint8), 20)]
+    cases += [rng.integers(0, 4, int(n), dtype=np.uint8) for n in rng.integers(2, 600, 40)]
+    cases += [rng.integers(0, 2, 300, dtype=np.uint8), rng.integers(0, 4, 5000, dtype=np.uint8)]
+    for t in cases:
+        s = bytes((t + 1).tolist()) + b"\x00"
+        want = sorted(range(len(s)), key=lambda i: s[i:])
+        assert mica.suffix_array(t).tolist() == want, len(t)
+
+
+def test_fm_entry_points_reject_bad_arguments():
+    from paper_1402_4876_amd import _lib
+    lib = _lib.load()
+    sa = np.zeros(4, np.uint32)
+    bad = np.array([0, 4, 1], np.uint8)
+    assert lib.mica_fm_suffix_array(bad.ctypes.data, 3, sa.ctypes.data) == -1
+    assert lib.mica_fm_suffix_array(None, 3, sa.ctypes.data) == -1
+    h = ctypes.c_void_p()
+    assert lib.mica_fm_create(0, None, 10, ctypes.byref(h)) == -1 and not h.value
+    b = _lib.FmBatch()
+    assert lib.mica_fm_search(None, ctypes.byref(b), None) == -1
+    assert lib.mica_fm_info(None, None, None) == -1
+    assert lib.mica_fm_destroy(None) == 0
