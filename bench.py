@@ -48,6 +48,8 @@ MEASURED_TRAFFIC = {
            round(9.89829e6 * 2048), round(5.19913e7 * 1024)),
     "ext": ("fd16b224fc48516df4060b6014ae6c449a82486f725cbe56051584b507e56327",
             round(4.13141e6 * 2048), round(1.00150e7 * 1024)),
+    # the search kernel, keyed by its own sources (fm_search.hip, fm_common.h)
+    "bwt": ("cb8ce1fa527c0ee992f34800e136c2176f5413d4ef1a1ef7a41b29ce351a5116", round(6.37592e6 * 2048), round(2.59487e4 * 1024)),
 }
 
 
@@ -89,7 +91,14 @@ WORKLOADS = {
            "launch, score + start/end + CIGAR", "mixed", True, False),
     "ext": ("1,000,000 seed extensions: read tails U{0..150} bp vs tail+32 bp windows, anchor score "
             "U{19..60}, clipping penalty 5, int16 + int32 re-run, score + start/end + CIGAR", "ext", True, False),
+    "bwt": ("few-mismatch search (k = 2, max_occ 64) of the 1,000,000 c1 reads of 150 bp against the whole "
+            "100 Mbp reference through its FM index", "bwt", False, False),
 }
+BWT_K, BWT_MAX_OCC = 2, 64
+# algorithmic bytes of one read's search: per backward-search step (one per
+# read base over the k + 1 parts) two 64-byte occurrence blocks, plus the
+# read's 2-bit words, its descriptor (12 B) and outputs (24 B)
+BWT_BYTES_PER_STEP = 128
 
 
 def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
@@ -237,6 +246,102 @@ def serving_bench(n_per_rate=2000, warmup=200, pool_size=32, slots=4, fracs=(0.3
     return out
 
 
+def bwt_bench(args):
+    """The few-mismatch search phase on the c1 reads and reference: reads/s,
+    HBM roofline of the search kernel, oracle baseline and parity sample."""
+    import torch
+
+    import oracle
+    import paper_1402_4876_amd as mica
+    import synth
+    from paper_1402_4876_amd import pack_codes
+    t0 = time.time()
+    b = synth.config1(**({"n_pairs": args.pairs} if args.pairs else {}))
+    log("generated reads and reference in %.1fs" % (time.time() - t0))
+    ix = mica.FmIndex(pack_codes(b.ref), len(b.ref))
+    info = ix.info()
+    log("FM index: %.1f s build, %.2f GB on the device" % (info["build_seconds"], info["device_bytes"] / 1e9))
+    reads2b = torch.from_numpy(pack_codes(b.reads).view(np.int32)).cuda()
+    read_off = torch.from_numpy(b.read_off).cuda()
+    read_len = torch.from_numpy(b.read_len).cuda()
+    n = b.n_pairs
+    out = {key: torch.empty(n, dtype=torch.int32, device="cuda") for key in ("best_mm", "n_best", "n_hits", "status")}
+    out["pos"] = torch.empty(n, dtype=torch.int64, device="cuda")
+
+    def step():
+        ix.search(reads2b, read_off, read_len, k=BWT_K, max_occ=BWT_MAX_OCC, reads_len=len(b.reads), out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # the search is one kernel launch on the current stream: events there time it
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(args.steps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    kernel_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    m = b.read_len.astype(np.int64)
+    alg = float((m * BWT_BYTES_PER_STEP + (m + 15) // 16 * 4 + 36).sum())
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_fm_search",
+            "kernel_ms": round(kernel_ms, 4), "bytes_per_read": round(alg / n, 1)}
+    meas = MEASURED_TRAFFIC.get("bwt")
+    if meas and meas[0] == fm_source_sha():
+        roof["traffic"] = meas[1] + meas[2]
+        roof["traffic_split"] = {"fetch": meas[1], "write": meas[2]}
+    else:
+        roof["traffic_note"] = "no FETCH_SIZE/WRITE_SIZE counters taken for this kernel source"
+    g = {key: v.cpu().numpy() for key, v in out.items()}
+    res = {
+        "metric": "reads/s (few-mismatch BWT search, k = 2)", "value": round(n / (ms * 1e-3), 1), "unit": "reads/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["bwt"][0], "name": "bwt", "reads": n, "ref_bases": len(b.ref),
+                   "index_build_s": round(info["build_seconds"], 1), "index_gb": round(info["device_bytes"] / 1e9, 3)},
+        "roofline": roof,
+        "found_frac": round(float((g["best_mm"] >= 0).mean()), 4),
+        "repetitive": int((g["status"] == mica.ST_REPETITIVE).sum()),
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        idx = np.arange(min(n, 64))
+        t0 = time.time()
+        o = oracle.kmm_search(b.ref, b.reads, b.read_off[idx], b.read_len[idx], k=BWT_K, max_occ=BWT_MAX_OCC,
+                              threads=threads)
+        dt = time.time() - t0
+        if dt < 4 and len(idx) < n:
+            idx = np.arange(min(n, int(len(idx) * 12 / max(dt, 1e-3))))
+            t0 = time.time()
+            o = oracle.kmm_search(b.ref, b.reads, b.read_off[idx], b.read_len[idx], k=BWT_K,
+                                  max_occ=BWT_MAX_OCC, threads=threads)
+            dt = time.time() - t0
+        mism = {key: int((g[key][idx].astype(np.int64) != o[key].astype(np.int64)).sum())
+                for key in ("best_mm", "n_best", "n_hits", "pos", "status")}
+        res["cpu_baseline"] = {"value": round(len(idx) / dt, 2), "unit": "reads/s", "cores": threads,
+                               "kind": "oracle", "sample": "first %d reads, every placement against the "
+                               "100 Mbp reference, %.1f s" % (len(idx), dt)}
+        res["parity_sample"] = {"reads": int(len(idx)), "mismatches": mism, "exact": all(v == 0 for v in mism.values())}
+    ix.close()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def fm_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fm_search.hip", "fm_common.h"):
+        with open(os.path.join(ROOT, "paper_1402_4876_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """A device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
     gives the counter-to-bytes factor used for the DP kernel's HBM traffic."""
@@ -273,6 +378,8 @@ def main():
                             slots=args.serve_slots, fifo_baseline=False)
         print(json.dumps({"serving": res}), flush=True)
         return 0
+    if args.gpus == 1 and args.config == "bwt":
+        return bwt_bench(args)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(pairs are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
