@@ -81,7 +81,16 @@ typedef struct {
   int32_t *best_mm, *n_best, *n_hits;
   int64_t *pos;
   uint32_t *status;
+  /* optional (NULL: not written): 3 entries per read, entry j the smallest
+   * placement (occurrence start minus the part's offset in the read) among
+   * the exact occurrences of part j, for j <= k when the part occurs at most
+   * max_occ times; MICA_FM_NO_CAND otherwise.  Placements may lie partly
+   * outside the reference.  These are the seeds of the DP windows of reads
+   * without a hit. */
+  int64_t *cand;
 } mica_fm_batch_t;
+
+#define MICA_FM_NO_CAND INT64_MIN
 
 /* Search every read of the batch (one kernel launch on the caller's
  * hipStream_t; asynchronous, allocates nothing). */

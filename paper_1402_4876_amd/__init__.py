@@ -21,12 +21,13 @@ from ._lib import (FORCE_INT32, MAX_READ_LEN, MAX_WIN_LEN, MODE_EXTEND, MODE_LOC
                    ST_REPETITIVE, ST_SATURATED, ST_WIN_OOB, MicaError)
 from .fm import FmIndex, suffix_array
 from .pack import pack_codes, unpack_words
+from .pipe import Pipeline
 from .serve import Server
 
 __all__ = ["Context", "Server", "align", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
            "PLAIN_LAUNCH", "NO_GRAPH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "MODE_EXTEND", "ST_SATURATED",
            "ST_CIGAR_TRUNC", "ST_LEN_LIMIT", "ST_WIN_OOB", "ST_READ_OOB", "ST_REPETITIVE", "MAX_READ_LEN",
-           "MAX_WIN_LEN", "FmIndex", "suffix_array"]
+           "MAX_WIN_LEN", "FmIndex", "suffix_array", "Pipeline"]
 
 
 def _stream_handle(stream):

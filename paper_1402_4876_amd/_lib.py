@@ -41,7 +41,8 @@ EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_p
            "mica_ctx_autotune", "mica_ctx_save_plan", "mica_ctx_load_plan", "mica_server_create",
            "mica_server_now", "mica_server_submit", "mica_server_poll", "mica_server_fetch", "mica_server_stats",
            "mica_server_reset_stats", "mica_server_destroy", "mica_last_error", "mica_fm_suffix_array",
-           "mica_fm_create", "mica_fm_destroy", "mica_fm_info", "mica_fm_search")
+           "mica_fm_create", "mica_fm_destroy", "mica_fm_info", "mica_fm_search", "mica_pipe_create",
+           "mica_pipe_run", "mica_pipe_destroy")
 
 
 class Scoring(ctypes.Structure):
@@ -90,7 +91,23 @@ class FmBatch(ctypes.Structure):
         ("read_len", ctypes.c_void_p), ("n_reads", ctypes.c_int64), ("k", ctypes.c_int32),
         ("max_occ", ctypes.c_int32), ("best_mm", ctypes.c_void_p), ("n_best", ctypes.c_void_p),
         ("n_hits", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("status", ctypes.c_void_p),
+        ("cand", ctypes.c_void_p),
     ]
+
+
+class PipeParams(ctypes.Structure):
+    """mica_pipe_params_t of include/mica_pipe.h."""
+    _fields_ = [("k", ctypes.c_int32), ("max_occ", ctypes.c_int32), ("band", ctypes.c_int32),
+                ("min_score", ctypes.c_int32), ("batch_reads", ctypes.c_int32), ("format_threads", ctypes.c_int32),
+                ("scoring", Scoring)]
+
+
+class PipeStats(ctypes.Structure):
+    """mica_pipe_stats_t of include/mica_pipe.h."""
+    _fields_ = [("reads", ctypes.c_int64), ("batches", ctypes.c_int64), ("mapped_search", ctypes.c_int64),
+                ("mapped_dp", ctypes.c_int64), ("unmapped", ctypes.c_int64), ("non_acgt", ctypes.c_int64),
+                ("repetitive", ctypes.c_int64), ("seconds", ctypes.c_double), ("parse_seconds", ctypes.c_double),
+                ("gpu_seconds", ctypes.c_double), ("format_seconds", ctypes.c_double)]
 
 
 def load():
@@ -145,6 +162,12 @@ def load():
     lib.mica_fm_search.argtypes = [P, ctypes.POINTER(FmBatch), P]
     for f in ("suffix_array", "create", "destroy", "info", "search"):
         getattr(lib, "mica_fm_" + f).restype = ctypes.c_int
+    lib.mica_pipe_create.argtypes = [ctypes.c_int, P, ctypes.c_uint64, ctypes.c_char_p, ctypes.POINTER(PipeParams),
+                                     ctypes.POINTER(P)]
+    lib.mica_pipe_run.argtypes = [P, ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(PipeStats)]
+    lib.mica_pipe_destroy.argtypes = [P]
+    for f in ("create", "run", "destroy"):
+        getattr(lib, "mica_pipe_" + f).restype = ctypes.c_int
     lib.mica_last_error.argtypes = []
     lib.mica_last_error.restype = ctypes.c_char_p
     _lib = lib

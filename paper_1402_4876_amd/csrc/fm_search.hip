@@ -25,6 +25,7 @@ struct FmSearchArgs {
   int32_t *best_mm, *n_best, *n_hits;
   int64_t* pos;
   uint32_t* status;
+  int64_t* cand;
 };
 
 __device__ __forceinline__ uint32_t base_at(const uint32_t* w, uint64_t p) {
@@ -127,8 +128,10 @@ __global__ __launch_bounds__(256) void k_fm_search(FmSearchArgs A) {
     if (lo < hi && hi - lo > (uint32_t)A.max_occ) {
       rep = 1;
     } else {
+      int64_t seed = MICA_FM_NO_CAND;
       for (uint32_t i = lo; i < hi; ++i) {
         const int64_t p = (int64_t)A.ix.sa[i] - a;
+        seed = (seed == MICA_FM_NO_CAND || p < seed) ? p : seed;
         if (p < 0 || (uint64_t)p + (uint64_t)m > A.ix.n) continue;
         // counted by the lowest-index exact part only (parts 0 and 1 are the
         // only ones below another part, k <= 2)
@@ -155,8 +158,10 @@ __global__ __launch_bounds__(256) void k_fm_search(FmSearchArgs A) {
           bp = p < bp ? p : bp;
         }
       }
+      if (A.cand) A.cand[r * 3 + j] = seed;
     }
   }
+  if (A.cand && live && j < 3 && (st != 0 || j > k || rep)) A.cand[r * 3 + j] = MICA_FM_NO_CAND;
   // the read's four lanes combine their hits
 #pragma unroll
   for (int x = 1; x < kLanesPerRead; x <<= 1) {
@@ -213,6 +218,7 @@ extern "C" mica_status_t mica_fm_search(mica_fm_t f, const mica_fm_batch_t* b, v
   A.n_hits = b->n_hits;
   A.pos = b->pos;
   A.status = b->status;
+  A.cand = b->cand;
   const int64_t threads = b->n_reads * kLanesPerRead;
   const int64_t blocks = (threads + 255) / 256;
   if (blocks > 0x7FFFFFFF) return fail(MICA_ERR_LIMIT, "too many reads for one launch");

@@ -51,7 +51,8 @@ class FmIndex:
         _lib.check(_lib.load().mica_fm_info(self._h, ctypes.byref(b), ctypes.byref(s)))
         return {"device_bytes": b.value, "build_seconds": s.value}
 
-    def search(self, reads2b, read_off, read_len, k=2, max_occ=64, reads_len=None, out=None, stream=None):
+    def search(self, reads2b, read_off, read_len, k=2, max_occ=64, reads_len=None, out=None, stream=None,
+               cand=False):
         """Search every read with at most ``k`` mismatches; returns a dict of
         tensors best_mm, n_best, n_hits (int32), pos (int64), status (int32
         bits).  Asynchronous on ``stream``."""
@@ -65,6 +66,8 @@ class FmIndex:
             out = {key: torch.empty(n, dtype=torch.int32, device=reads2b.device)
                    for key in ("best_mm", "n_best", "n_hits", "status")}
             out["pos"] = torch.empty(n, dtype=torch.int64, device=reads2b.device)
+        if cand and "cand" not in out:
+            out["cand"] = torch.empty((n, 3), dtype=torch.int64, device=reads2b.device)
         b = _lib.FmBatch()
         b.reads2b = reads2b.data_ptr()
         b.reads_len = int(reads_len) if reads_len is not None else reads2b.numel() * 16
@@ -75,6 +78,7 @@ class FmIndex:
         b.max_occ = int(max_occ)
         for key in ("best_mm", "n_best", "n_hits", "pos", "status"):
             setattr(b, key, out[key].data_ptr())
+        b.cand = out["cand"].data_ptr() if "cand" in out else None
         s = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         if stream is None:
             s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)

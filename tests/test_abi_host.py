@@ -34,8 +34,10 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     from paper_1402_4876_amd import _lib
     structs = {"mica_batch_t": _lib.Batch, "mica_scoring_t": _lib.Scoring, "mica_batch_stats_t": _lib.BatchStats,
-               "mica_tune_entry_t": _lib.TuneEntry, "mica_fm_batch_t": _lib.FmBatch}
+               "mica_tune_entry_t": _lib.TuneEntry, "mica_fm_batch_t": _lib.FmBatch,
+               "mica_pipe_params_t": _lib.PipeParams, "mica_pipe_stats_t": _lib.PipeStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mica_dp.h"', '#include "mica_fm.h"',
+             '#include "mica_pipe.h"',
              'int main(void) {']
     for cname, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -132,3 +134,10 @@ def test_fm_entry_points_reject_bad_arguments():
     assert lib.mica_fm_search(None, ctypes.byref(b), None) == -1
     assert lib.mica_fm_info(None, None, None) == -1
     assert lib.mica_fm_destroy(None) == 0
+    prm = _lib.PipeParams()
+    assert lib.mica_pipe_create(0, None, 10, b"ref", ctypes.byref(prm), ctypes.byref(h)) == -1 and not h.value
+    words = np.zeros(4, np.uint32)
+    assert lib.mica_pipe_create(0, words.ctypes.data, 10, b"ref", ctypes.byref(prm), ctypes.byref(h)) == -1
+    assert b"out of range" in lib.mica_last_error()
+    assert lib.mica_pipe_run(None, b"a.fq", b"b.sam", None) == -1
+    assert lib.mica_pipe_destroy(None) == 0
