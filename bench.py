@@ -93,8 +93,12 @@ WORKLOADS = {
             "U{19..60}, clipping penalty 5, int16 + int32 re-run, score + start/end + CIGAR", "ext", True, False),
     "bwt": ("few-mismatch search (k = 2, max_occ 64) of the 1,000,000 c1 reads of 150 bp against the whole "
             "100 Mbp reference through its FM index", "bwt", False, False),
+    "pipe": ("host pipeline: the 1,000,000 c1 reads of 150 bp as a FASTQ file through the few-mismatch search "
+             "(k = 2) and semi-global DP of seed windows (band 32) into a SAM file, 100 Mbp reference",
+             "pipe", True, False),
 }
 BWT_K, BWT_MAX_OCC = 2, 64
+PIPE_BAND = 32
 # algorithmic bytes of one read's search: per backward-search step (one per
 # read base over the k + 1 parts) two 64-byte occurrence blocks, plus the
 # read's 2-bit words, its descriptor (12 B) and outputs (24 B)
@@ -333,6 +337,57 @@ def bwt_bench(args):
     return 0
 
 
+def pipe_bench(args):
+    """End-to-end host pipeline: FASTQ file in, SAM file out (files in TMPDIR)."""
+    import shutil
+    import tempfile
+
+    import paper_1402_4876_amd as mica
+    import synth
+    from paper_1402_4876_amd import pack_codes
+    t0 = time.time()
+    b = synth.config1(**({"n_pairs": args.pairs} if args.pairs else {}))
+    tmp = tempfile.mkdtemp(prefix="mica_pipe_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        fq = os.path.join(tmp, "reads.fq")
+        sam = os.path.join(tmp, "out.sam")
+        letters = np.frombuffer(b"ACGT", np.uint8)
+        with open(fq, "wb") as f:
+            qual = b"I" * 150
+            seqs = letters[b.reads]
+            for r in range(b.n_pairs):
+                o = int(b.read_off[r])
+                m = int(b.read_len[r])
+                f.write(b"@r%d\n%s\n+\n%s\n" % (r, seqs[o:o + m].tobytes(), qual[:m]))
+        fq_bytes = os.path.getsize(fq)
+        log("wrote %d reads as FASTQ (%.0f MB) in %.1fs" % (b.n_pairs, fq_bytes / 1e6, time.time() - t0))
+        pipe = mica.Pipeline(pack_codes(b.ref), len(b.ref), "chrS", k=BWT_K, max_occ=BWT_MAX_OCC, band=PIPE_BAND,
+                             min_score=0, batch_reads=1 << 18, format_threads=8)
+        for _ in range(args.warmup):
+            pipe.run(fq, sam)
+        runs = []
+        for _ in range(max(1, args.steps)):
+            runs.append(pipe.run(fq, sam))
+        pipe.close()
+        sam_bytes = os.path.getsize(sam)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    st = runs[-1]
+    sec = float(np.mean([r["seconds"] for r in runs]))
+    res = {
+        "metric": "reads/s (FASTQ to SAM, both phases)", "value": round(b.n_pairs / sec, 1), "unit": "reads/s",
+        "n_gpus": 1, "steps": len(runs), "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i16", "data": "synthetic",
+        "config": {"workload": WORKLOADS["pipe"][0], "name": "pipe", "reads": b.n_pairs, "batch_reads": 1 << 18,
+                   "fastq_mb": round(fq_bytes / 1e6, 1), "sam_mb": round(sam_bytes / 1e6, 1)},
+        "stages_s": {"parse": round(st["parse_seconds"], 3), "gpu": round(st["gpu_seconds"], 3),
+                     "format_write": round(st["format_seconds"], 3), "wall": round(st["seconds"], 3)},
+        "reads_by_outcome": {"search": st["mapped_search"], "dp": st["mapped_dp"], "unmapped": st["unmapped"]},
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def fm_source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -380,6 +435,8 @@ def main():
         return 0
     if args.gpus == 1 and args.config == "bwt":
         return bwt_bench(args)
+    if args.gpus == 1 and args.config == "pipe":
+        return pipe_bench(args)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(pairs are independent; see the sharding notes). Run with --gpus 1.", file=sys.stderr)
