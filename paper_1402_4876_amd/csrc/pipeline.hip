@@ -213,15 +213,19 @@ struct LineReader {
   }
 };
 
-inline int code_of(char c) {
-  switch (c) {
-    case 'A': case 'a': return 0;
-    case 'C': case 'c': return 1;
-    case 'G': case 'g': return 2;
-    case 'T': case 't': return 3;
-    default: return -1;
+// base code of a FASTQ letter (A0 C1 G2 T3, either case), -1 for any other
+struct CodeTable {
+  int8_t v[256];
+  CodeTable() {
+    for (int i = 0; i < 256; ++i) v[i] = -1;
+    v['A'] = v['a'] = 0;
+    v['C'] = v['c'] = 1;
+    v['G'] = v['g'] = 2;
+    v['T'] = v['t'] = 3;
   }
-}
+};
+const CodeTable kCodes;
+inline int code_of(char c) { return kCodes.v[(uint8_t)c]; }
 
 struct Slot {
   hipStream_t stream = nullptr;
@@ -359,8 +363,9 @@ mica_status_t ensure_words(Slot& s, size_t words) {
   return MICA_OK;
 }
 
-// parse up to max_reads FASTQ records; *bad set for malformed input
-std::unique_ptr<HostBatch> parse_batch(LineReader& in, int64_t max_reads, bool* bad) {
+// parse up to max_reads FASTQ records (record lines on this thread, the 2-bit
+// packing on `threads` threads); *bad set for malformed input
+std::unique_ptr<HostBatch> parse_batch(LineReader& in, int64_t max_reads, int threads, bool* bad) {
   auto b = std::make_unique<HostBatch>();
   const char* s;
   size_t n;
@@ -407,23 +412,38 @@ std::unique_ptr<HostBatch> parse_batch(LineReader& in, int64_t max_reads, bool* 
     tot += ((uint64_t)b->len[r] + 15) / 16 * 16;
   }
   b->words.assign(std::max<uint64_t>(tot / 16, 1), 0u);
-  for (int64_t r = 0; r < b->n; ++r) {
-    const char* sq = b->text.data() + b->seq_off[r];
-    const int m = b->len[r];
-    uint32_t* w = b->words.data() + b->roff[r] / 16;
-    bool ok = true;
-    for (int t = 0; t < m; ++t) {
-      const int c = code_of(sq[t]);
-      if (c < 0) {
-        ok = false;
-        break;
+  std::vector<int32_t> part_max((size_t)threads, 0);
+  auto pack = [&](int th, int64_t lo, int64_t hi) {
+    int32_t mx = 0;
+    for (int64_t r = lo; r < hi; ++r) {
+      const char* sq = b->text.data() + b->seq_off[r];
+      const int m = b->len[r];
+      uint32_t* w = b->words.data() + b->roff[r] / 16;
+      bool ok = true;
+      for (int t0 = 0; t0 < m && ok; t0 += 16) {
+        uint32_t word = 0;
+        const int e = std::min(m - t0, 16);
+        for (int t = 0; t < e; ++t) {
+          const int c = code_of(sq[t0 + t]);
+          ok = ok && c >= 0;
+          word |= (uint32_t)(c & 3) << (2 * t);
+        }
+        w[t0 >> 4] = word;
       }
-      w[t >> 4] |= (uint32_t)c << (2 * (t & 15));
+      b->non_acgt[r] = ok ? 0 : 1;
+      b->dlen[r] = ok ? m : 0;
+      if (ok) mx = std::max(mx, m);
     }
-    b->non_acgt[r] = ok ? 0 : 1;
-    b->dlen[r] = ok ? m : 0;
-    if (ok) b->max_m = std::max(b->max_m, m);
-  }
+    part_max[(size_t)th] = mx;
+  };
+  const int T = (int)std::max<int64_t>(1, std::min<int64_t>(threads, b->n / 4096 + 1));
+  const int64_t chunk = (b->n + T - 1) / T;
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t)
+    th.emplace_back(pack, t, std::min<int64_t>(b->n, t * chunk), std::min<int64_t>(b->n, (t + 1) * chunk));
+  pack(0, 0, std::min<int64_t>(b->n, chunk));
+  for (auto& x : th) x.join();
+  for (int32_t v : part_max) b->max_m = std::max(b->max_m, v);
   return b;
 }
 
@@ -667,7 +687,7 @@ extern "C" mica_status_t mica_pipe_run(mica_pipe_t P, const char* fastq_path, co
     for (;;) {
       const auto tp = std::chrono::steady_clock::now();
       bool bad = false;
-      BatchPtr b = parse_batch(in, P->prm.batch_reads, &bad);
+      BatchPtr b = parse_batch(in, P->prm.batch_reads, P->prm.format_threads, &bad);
       parse_s += since(tp);
       if (bad) {
         set_err(MICA_ERR_INVALID_ARG, "malformed FASTQ record");
