@@ -208,3 +208,31 @@ def test_pipeline_rejects_malformed_fastq(tmp_path):
     line = [l for l in open(tmp_path / "out.sam").read().split("\n") if l.startswith("r1")][0]
     assert line.split("\t")[3] == "101" and line.split("\t")[5] == "60M"
     pipe.close()
+
+
+def test_pipeline_input_forms(tmp_path):
+    """CRLF line ends, blank lines between records, a missing final newline
+    and lower-case bases give the same alignments as the plain file."""
+    import paper_1402_4876_amd as mica
+    ref = _reference()
+    recs = _records(ref, n=600, seed=14)[:-2]
+    plain = tmp_path / "plain.fq"
+    _write_fastq(plain, recs)
+    odd = tmp_path / "odd.fq"
+    body = "\r\n\r\n".join("@%s\r\n%s\r\n+\r\n%s" % r for r in recs)  # blank lines between records
+    odd.write_bytes(body.encode())                                             # and no final newline
+    low = tmp_path / "low.fq"
+    with open(low, "w") as f:
+        for name, seq, qual in recs:
+            f.write("@%s\n%s\n+%s\n%s\n" % (name, seq.lower(), name, qual))
+    pipe = mica.Pipeline(pack_codes(ref), len(ref), "chrT", batch_reads=250, format_threads=2)
+    outs = {}
+    for tag, fq in (("plain", plain), ("odd", odd), ("low", low)):
+        pipe.run(fq, tmp_path / (tag + ".sam"))
+        outs[tag] = [l.split("\t") for l in open(tmp_path / (tag + ".sam")).read().split("\n")
+                     if l and not l.startswith("@")]
+    pipe.close()
+    assert outs["plain"] == outs["odd"]
+    assert len(outs["low"]) == len(outs["plain"])
+    for a, b in zip(outs["plain"], outs["low"]):
+        assert a[:9] == b[:9] and a[10:] == b[10:] and a[9].lower() == b[9]
