@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {
     "ext": ("fd16b224fc48516df4060b6014ae6c449a82486f725cbe56051584b507e56327",
             round(4.13141e6 * 2048), round(1.00150e7 * 1024)),
     # the search kernel, keyed by its own sources (fm_search.hip, fm_common.h)
-    "bwt": ("cb8ce1fa527c0ee992f34800e136c2176f5413d4ef1a1ef7a41b29ce351a5116", round(6.37592e6 * 2048), round(2.59487e4 * 1024)),
+    "bwt": ("e51dba48c50b365e3927de4f770d2699994e5edfa1a080f0baae8ed9022d5f76", round(6.27857e6 * 2048), round(2.58946e4 * 1024)),
 }
 
 
