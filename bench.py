@@ -141,9 +141,23 @@ def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
         ncig = np.minimum(np.abs(o["n_cigar"]), cap)
         col = np.arange(cap)[None, :] < ncig[:, None]
         mism["cigar"] = int((((gpu_out["cigar"][idx].astype(np.uint32) != o["cigar"]) & col).any(axis=1)).sum())
+    # one core on the first 10,000 pairs
+    i1 = np.arange(min(batch.n_pairs, 10000))
+    t1c = time.time()
+    oracle.align_batch(batch.ref, batch.win_off[i1], batch.win_len[i1], batch.reads, batch.read_off[i1],
+                       batch.read_len[i1], batch.mode[i1], sc, trace=want_trace, threads=1, h0=h0[i1], **ext)
+    dt1 = time.time() - t1c
+    cells1 = float(np.dot(batch.read_len[i1].astype(np.int64), batch.win_len[i1].astype(np.int64)))
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     base = {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
             "sample": "first %d pairs of the same batch (%.3g cells), %s, %.1f s" % (
-                n, cells, "with traceback" if want_trace else "score + end", dt)}
+                n, cells, "with traceback" if want_trace else "score + end", dt),
+            "single_core_gcups": round(cells1 / dt1 / 1e9, 4), "cpu_model": cpu_model}
     parity = {"pairs": n, "mismatches": mism, "exact": all(v == 0 for v in mism.values())}
     return base, parity
 
@@ -486,16 +500,37 @@ def main():
     torch.cuda.synchronize()
     ctx.set_timing(True)
     ctx.read_timing()
+    # events on the launch stream around every step (the align call enqueues
+    # the whole graph there): per-step device times for the median and minimum
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
     fill_ms, nb = ctx.read_timing()
     ctx.set_timing(False)
     stats = ctx.last_stats()
     ms = (t1 - t0) * 1e3 / args.steps
+    # transfers of the same batch, timed apart from the steps: inputs from
+    # pinned host memory to the device, outputs back
+    host_in = {k: v.cpu().pin_memory() for k, v in dev.items() if isinstance(v, torch.Tensor)}
+    host_out = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True) for k, v in out.items()}
+    te = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    te[0].record()
+    for k, v in host_in.items():
+        dev[k].copy_(v, non_blocking=True)
+    te[1].record()
+    for k, v in out.items():
+        host_out[k].copy_(v, non_blocking=True)
+    te[2].record()
+    torch.cuda.synchronize()
+    h2d_ms, d2h_ms = te[0].elapsed_time(te[1]), te[1].elapsed_time(te[2])
     gcups = cells / (ms * 1e-3) / 1e9
     fill_avg_ms = fill_ms / max(nb, 1)
     if mode_kind == "mixed":
@@ -526,6 +561,12 @@ def main():
                    "launch": "plain per-bucket" if args.plain else (
                        "one class: its own kernel" if one_class else "persistent")},
         "roofline": roof,
+        "step_ms": {"median": round(step_ms[len(step_ms) // 2], 4), "min": round(step_ms[0], 4),
+                    "max": round(step_ms[-1], 4)},
+        "transfers": {"h2d_ms": round(h2d_ms, 3), "d2h_ms": round(d2h_ms, 3),
+                      "h2d_mb": round(sum(v.numel() * v.element_size() for v in host_in.values()) / 1e6, 1),
+                      "d2h_mb": round(sum(v.numel() * v.element_size() for v in out.values()) / 1e6, 1),
+                      "gcups_with_transfers": round(cells / ((ms + h2d_ms + d2h_ms) * 1e-3) / 1e9, 2)},
         "saturated_pairs": int(stats["n_saturated"]),
         "resident_waves": int(stats["n_waves"]),
     }
