@@ -49,7 +49,7 @@ __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
 // classes 0..kPersistSmallMax, part 1 the classes up to kPersistMaxClass.
 // The other buckets run as plain per-bucket launches after them.
 #ifndef MICA_PERSIST_MAX_CLASS
-#define MICA_PERSIST_MAX_CLASS 13
+#define MICA_PERSIST_MAX_CLASS 15
 #endif
 constexpr int kPersistSmallMax = 9;
 constexpr int kPersistMaxClass = MICA_PERSIST_MAX_CLASS;

@@ -1,4 +1,4 @@
-// Persistent fill kernel: with traceback, local, reads of 161 to 224 bases.
+// Persistent fill kernel: with traceback, local, reads of 161 to 256 bases.
 #include "dp_fill.h"
 
 namespace mica {
