@@ -93,7 +93,8 @@ typedef struct {
 #define MICA_FM_NO_CAND INT64_MIN
 
 /* Search every read of the batch (one kernel launch on the caller's
- * hipStream_t; asynchronous, allocates nothing). */
+ * hipStream_t; asynchronous, allocates nothing).  The index is read only:
+ * calls from several host threads or on several streams may overlap. */
 mica_status_t mica_fm_search(mica_fm_t fm, const mica_fm_batch_t *batch, void *stream);
 
 #ifdef __cplusplus

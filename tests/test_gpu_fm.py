@@ -174,3 +174,36 @@ def test_full_size_workload_sampled():
     hit = g["best_mm"] >= 0
     assert 0.3 < hit.mean() < 0.8  # reads with indels or > 2 substitutions go on to DP
     ix.close()
+
+
+def test_search_argument_errors(small):
+    """Bad k, max_occ or arrays are refused before any launch; an empty batch is a no-op."""
+    import paper_1402_4876_amd as mica
+    ref, ix = small
+    reads = _reads(ref, seed=8, n=10)
+    flat, off, m, dev = _upload(reads)
+    for k, mo in ((3, 64), (-1, 64), (2, 0), (2, 70000)):
+        with pytest.raises(mica.MicaError):
+            ix.search(dev[0], dev[1], dev[2], k=k, max_occ=mo, reads_len=len(flat))
+    with pytest.raises(ValueError):
+        ix.search(dev[0], dev[1], dev[2][:5], k=2)
+    e = ix.search(dev[0], dev[1][:0], dev[2][:0], k=2, reads_len=len(flat))
+    torch.cuda.synchronize()
+    assert e["best_mm"].numel() == 0
+
+
+def test_concurrent_streams(small):
+    """Two batches searched at once on two streams equal their one-by-one results."""
+    ref, ix = small
+    a = _upload(_reads(ref, seed=9, n=800))
+    b = _upload(_reads(ref, seed=10, n=900))
+    ga = _gpu(ix, a[3], len(a[0]), 2, 64)
+    gb = _gpu(ix, b[3], len(b[0]), 2, 64)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        oa = ix.search(a[3][0], a[3][1], a[3][2], k=2, max_occ=64, reads_len=len(a[0]), stream=s1)
+    with torch.cuda.stream(s2):
+        ob = ix.search(b[3][0], b[3][1], b[3][2], k=2, max_occ=64, reads_len=len(b[0]), stream=s2)
+    torch.cuda.synchronize()
+    for key in KEYS:
+        assert np.array_equal(oa[key].cpu().numpy(), ga[key]) and np.array_equal(ob[key].cpu().numpy(), gb[key])
