@@ -269,7 +269,6 @@ def bwt_bench(args):
     HBM roofline of the search kernel, oracle baseline and parity sample."""
     import torch
 
-    import oracle
     import paper_1402_4876_amd as mica
     import synth
     from paper_1402_4876_amd import pack_codes
@@ -328,6 +327,7 @@ def bwt_bench(args):
         "repetitive": int((g["status"] == mica.ST_REPETITIVE).sum()),
     }
     if not args.no_cpu_baseline:
+        import oracle
         threads = min(16, os.cpu_count() or 1)
         idx = np.arange(min(n, 64))
         t0 = time.time()
