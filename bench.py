@@ -105,6 +105,37 @@ PIPE_BAND = 32
 BWT_BYTES_PER_STEP = 128
 
 
+def small_batch_latency(ctx, reps=50):
+    """Per-call latency of the 1,000-pair, 150 x 200 int32 batch (too small to
+    fill the GPU): host time from the call to its completion, median and min."""
+    import torch
+
+    import paper_1402_4876_amd as mica
+    import synth
+    b = synth.config0()
+    dev = mica.to_device(b)
+    n = b.n_pairs
+    out = {k: torch.empty(n, dtype=torch.int32, device="cuda") for k in ("score", "read_end", "ref_end", "status")}
+    mm, nn = int(b.read_len.max()), int(b.win_len.max())
+
+    def call():
+        mica.align(ctx, dev["ref2b"], dev["win_off"], dev["win_len"], dev["reads2b"], dev["read_off"],
+                   dev["read_len"], force_int32=True, max_read_len=mm, max_win_len=nn, ref_len=dev["ref_len"],
+                   reads_len=dev["reads_len"], out=out)
+        torch.cuda.synchronize()
+
+    for _ in range(5):
+        call()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        call()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return {"workload": "1,000 pairs, 150 x 200, int32, score + end (one graph launch, synchronised)",
+            "median_ms": round(ts[len(ts) // 2], 3), "min_ms": round(ts[0], 3)}
+
+
 def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
     """Time the CPU oracle on a bounded sample of the same pairs (all host cores up to 16)."""
     import oracle
@@ -570,6 +601,8 @@ def main():
         "saturated_pairs": int(stats["n_saturated"]),
         "resident_waves": int(stats["n_waves"]),
     }
+    if args.config == "c1":
+        res["small_batch_latency"] = small_batch_latency(ctx)
     if not args.no_serving:
         res["serving"] = serving_bench(n_per_rate=args.serve_requests, warmup=max(args.serve_requests // 10, 20),
                                        slots=args.serve_slots)

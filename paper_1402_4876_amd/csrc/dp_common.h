@@ -38,6 +38,19 @@ __host__ __device__ constexpr int bucket_id(int kind, int cls, int mode) {
 __host__ __device__ constexpr int bucket_kind(int b) { return b / (kNumModes * kNumClasses); }
 __host__ __device__ constexpr int bucket_class(int b) { return (b / kNumModes) % kNumClasses; }
 __host__ __device__ constexpr int bucket_mode(int b) { return b % kNumModes; }
+// Within a bucket pairs are ordered by read length, longest first, in
+// kSubBins bins of the dummy-row count d0 (one bin per row for the 16-lane
+// classes, 16 rows per bin for the 64-lane ones, the last bin open-ended).
+// A work item then holds reads of nearly equal length and, since windows
+// usually grow with the read, nearly equal windows: its step count (the
+// longest window of its pairs) wastes less on its shorter pairs, and the
+// longest items of a bucket are taken first.
+constexpr int kSubBins = 16;
+constexpr int kNumSubBuckets = kNumBuckets * kSubBins;
+__host__ __device__ constexpr int sub_bin(int cls, int d0) {
+  return (class_lanes(cls) == 16 ? d0 : d0 >> 4) < kSubBins - 1 ? (class_lanes(cls) == 16 ? d0 : d0 >> 4)
+                                                                 : kSubBins - 1;
+}
 // pairs handled by one wave-sized work item
 __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
   return (kind == kK32 ? 1 : 2) * (64 / class_lanes(cls));
@@ -130,12 +143,13 @@ struct Params {
   int32_t mode_mask;       // modes the batch may hold (bit per mode)
   uint32_t flags;
   // workspace (device memory of the context)
-  uint32_t* bucket_of;         // [n_pairs]
-  uint32_t* sorted;            // [n_pairs] pair ids grouped by bucket
+  uint32_t* bucket_of;         // [n_pairs] bucket * kSubBins + sub-bin, or kSkip
+  uint32_t* sorted;            // [n_pairs] pair ids grouped by bucket, then sub-bin
   uint32_t* rerun;             // [n_pairs] pair ids to recompute with 32-bit scores
   uint32_t* bcount;            // [kNumBuckets]
   uint32_t* bstart;            // [kNumBuckets]
-  uint32_t* bfill;             // [kNumBuckets]
+  uint32_t* scount;            // [kNumSubBuckets] pairs per (bucket, sub-bin)
+  uint32_t* sfill;             // [kNumSubBuckets] next free position of each (bucket, sub-bin)
   uint32_t* qstart;            // [kNumBuckets + 1] first item of each queue position
   const uint32_t* qorder;      // [kNumBuckets] bucket served at each queue position
   const uint8_t* class_of_m;   // [kMaxM + 1]

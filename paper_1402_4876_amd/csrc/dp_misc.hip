@@ -30,12 +30,9 @@ __global__ __launch_bounds__(256) void k_rerun(const Params* __restrict__ prm) {
 // planning: validation, trivial pairs, bucket histogram, work queue
 
 __global__ void k_zero(const Params* __restrict__ prm) {
+  for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x) prm->scount[i] = 0;
   const int i = threadIdx.x;
-  if (i < kNumBuckets) {
-    prm->bcount[i] = 0;
-    prm->bfill[i] = 0;
-    prm->bhead[i] = 0;
-  }
+  if (i < kNumBuckets) prm->bhead[i] = 0;
   if (i < kNumCounters) prm->counters[i] = 0;
 }
 
@@ -60,8 +57,8 @@ __device__ __forceinline__ bool int16_safe(int m, int n, int mode, int d0, int a
 }
 
 __global__ __launch_bounds__(256) void k_plan(const Params* __restrict__ prm) {
-  __shared__ uint32_t hist[kNumBuckets];
-  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x) hist[i] = 0;
+  __shared__ uint32_t hist[kNumSubBuckets];
+  for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < prm->n_pairs) {
@@ -111,40 +108,66 @@ __global__ __launch_bounds__(256) void k_plan(const Params* __restrict__ prm) {
       int kind;
       if (prm->flags & kForceInt32) kind = kK32;
       else kind = int16_safe(m, n, md, d0, prm->sa, prm->sb, prm->so, prm->se, h0) ? kK16 : kK16Sat;
-      b = (uint32_t)bucket_id(kind, cls, md);
+      b = (uint32_t)(bucket_id(kind, cls, md) * kSubBins + sub_bin(cls, d0));
       atomicAdd(&hist[b], 1u);
     }
     prm->bucket_of[p] = b;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x)
-    if (hist[i]) atomicAdd(&prm->bcount[i], hist[i]);
+  for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x)
+    if (hist[i]) atomicAdd(&prm->scount[i], hist[i]);
 }
 
-__global__ void k_scan(const Params* __restrict__ prm) {
-  if (threadIdx.x != 0) return;
-  uint32_t acc = 0;
-  for (int b = 0; b < kNumBuckets; ++b) {
-    prm->bstart[b] = acc;
-    acc += prm->bcount[b];
+// One block of kScanThreads: bucket sizes and starts, the start of every
+// (bucket, sub-bin) run inside its bucket, and the work-queue positions.
+constexpr int kScanThreads = 256;
+static_assert(kNumBuckets <= kScanThreads, "one thread per bucket");
+__global__ __launch_bounds__(kScanThreads) void k_scan(const Params* __restrict__ prm) {
+  __shared__ uint32_t cnt[kNumBuckets];
+  __shared__ uint32_t start[kNumBuckets];
+  const int b = threadIdx.x;
+  uint32_t sub[kSubBins];
+  if (b < kNumBuckets) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int s = 0; s < kSubBins; ++s) {
+      sub[s] = acc;
+      acc += prm->scount[b * kSubBins + s];
+    }
+    cnt[b] = acc;
+    prm->bcount[b] = acc;
   }
-  uint32_t items = 0;
-  for (int q = 0; q < kNumBuckets; ++q) {
-    const int b = (int)prm->qorder[q];
-    prm->qstart[q] = items;
-    const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), bucket_class(b));
-    items += (prm->bcount[b] + ppi - 1) / ppi;
+  __syncthreads();
+  if (b == 0) {
+    uint32_t acc = 0;
+    for (int i = 0; i < kNumBuckets; ++i) {
+      start[i] = acc;
+      acc += cnt[i];
+    }
+    uint32_t items = 0;
+    for (int q = 0; q < kNumBuckets; ++q) {
+      const int bq = (int)prm->qorder[q];
+      prm->qstart[q] = items;
+      const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(bq), bucket_class(bq));
+      items += (cnt[bq] + ppi - 1) / ppi;
+    }
+    prm->qstart[kNumBuckets] = items;
+    prm->counters[kCtrItems] = items;
+    for (int q = 0; q < kPersistParts; ++q) prm->counters[kCtrQueueHead + q] = 0;
+    prm->counters[kCtrRerun] = 0;
   }
-  prm->qstart[kNumBuckets] = items;
-  prm->counters[kCtrItems] = items;
-  for (int q = 0; q < kPersistParts; ++q) prm->counters[kCtrQueueHead + q] = 0;
-  prm->counters[kCtrRerun] = 0;
+  __syncthreads();
+  if (b < kNumBuckets) {
+    prm->bstart[b] = start[b];
+#pragma unroll
+    for (int s = 0; s < kSubBins; ++s) prm->sfill[b * kSubBins + s] = start[b] + sub[s];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_scatter(const Params* __restrict__ prm) {
-  __shared__ uint32_t cnt[kNumBuckets];
-  __shared__ uint32_t base[kNumBuckets];
-  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x) cnt[i] = 0;
+  __shared__ uint32_t cnt[kNumSubBuckets];
+  __shared__ uint32_t base[kNumSubBuckets];
+  for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t b = kSkip, rank = 0;
@@ -153,10 +176,10 @@ __global__ __launch_bounds__(256) void k_scatter(const Params* __restrict__ prm)
     if (b != kSkip) rank = atomicAdd(&cnt[b], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kNumBuckets; i += blockDim.x)
-    base[i] = cnt[i] ? atomicAdd(&prm->bfill[i], cnt[i]) : 0;
+  for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x)
+    base[i] = cnt[i] ? atomicAdd(&prm->sfill[i], cnt[i]) : 0;
   __syncthreads();
-  if (b != kSkip) prm->sorted[prm->bstart[b] + base[b] + rank] = (uint32_t)p;
+  if (b != kSkip) prm->sorted[base[b] + rank] = (uint32_t)p;
 }
 
 __global__ __launch_bounds__(256) void k_pack2bit(const uint8_t* __restrict__ codes, int64_t n,

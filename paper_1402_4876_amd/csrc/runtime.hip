@@ -28,12 +28,13 @@ namespace {
 
 uint32_t* small_bcount(mica_ctx* c) { return c->d_small; }
 uint32_t* small_bstart(mica_ctx* c) { return c->d_small + kNumBuckets; }
-uint32_t* small_bfill(mica_ctx* c) { return c->d_small + 2 * kNumBuckets; }
-uint32_t* small_qstart(mica_ctx* c) { return c->d_small + 3 * kNumBuckets; }         // +1 entry
-uint32_t* small_qorder(mica_ctx* c) { return c->d_small + 4 * kNumBuckets + 8; }
-uint32_t* small_counters(mica_ctx* c) { return c->d_small + 5 * kNumBuckets + 8; }
-uint32_t* small_bhead(mica_ctx* c) { return c->d_small + 5 * kNumBuckets + 8 + kNumCounters; }
-constexpr size_t kSmallWords = 6 * kNumBuckets + 8 + kNumCounters;
+uint32_t* small_qstart(mica_ctx* c) { return c->d_small + 2 * kNumBuckets; }         // +1 entry
+uint32_t* small_qorder(mica_ctx* c) { return c->d_small + 3 * kNumBuckets + 8; }
+uint32_t* small_counters(mica_ctx* c) { return c->d_small + 4 * kNumBuckets + 8; }
+uint32_t* small_bhead(mica_ctx* c) { return c->d_small + 4 * kNumBuckets + 8 + kNumCounters; }
+uint32_t* small_scount(mica_ctx* c) { return c->d_small + 5 * kNumBuckets + 8 + kNumCounters; }
+uint32_t* small_sfill(mica_ctx* c) { return small_scount(c) + kNumSubBuckets; }
+constexpr size_t kSmallWords = 5 * kNumBuckets + 8 + kNumCounters + 2 * kNumSubBuckets;
 
 // cost of one work item of a bucket, for the descending work-queue order
 double bucket_cost(int b) {
@@ -459,7 +460,8 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.rerun = c->d_pairs + 2 * c->pair_cap;
   P.bcount = small_bcount(c);
   P.bstart = small_bstart(c);
-  P.bfill = small_bfill(c);
+  P.scount = small_scount(c);
+  P.sfill = small_sfill(c);
   P.qstart = small_qstart(c);
   P.qorder = small_qorder(c);
   P.class_of_m = c->d_class;
@@ -480,7 +482,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   std::vector<Launch> seq;
   seq.push_back({K.zero, 1, 256, 0, false});
   seq.push_back({K.plan, pblocks, 256, 0, false});
-  seq.push_back({K.scan, 1, 64, 0, false});
+  seq.push_back({K.scan, 1, 256, 0, false});
   seq.push_back({K.scatter, pblocks, 256, 0, false});
   for (size_t i = 0; i < fills.size(); ++i) {
     // each fill kernel gets the blocks it keeps resident (its waves index
