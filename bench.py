@@ -44,10 +44,10 @@ KERNEL_SOURCES = ("dp_fill.h", "dp_common.h")
 MEASURED_TRAFFIC = {
     # config: (kernel source sha256, fetch bytes, write bytes); for the
     # extension workload the sums over its fill launches and re-run
-    "c1": ("b2d25f5e0ca1b74fa13b0c09d18457e38f8c2b7e48c05ace4633385a49441be6",
-           round(9.89752e6 * 2048), round(5.19912e7 * 1024)),
-    "ext": ("b2d25f5e0ca1b74fa13b0c09d18457e38f8c2b7e48c05ace4633385a49441be6",
-            round(4.11187e6 * 2048), round(1.00150e7 * 1024)),
+    "c1": ("621b788045304b7fc41f002f0a84c925aaf3272b4b61ff4ff1f8522608e199e4",
+           round(9.91021e6 * 2048), round(5.19912e7 * 1024)),
+    "ext": ("621b788045304b7fc41f002f0a84c925aaf3272b4b61ff4ff1f8522608e199e4",
+            round(4.4131e6 * 2048), round(9.70931e6 * 1024)),
     # the search kernel, keyed by its own sources (fm_search.hip, fm_common.h)
     "bwt": ("e51dba48c50b365e3927de4f770d2699994e5edfa1a080f0baae8ed9022d5f76", round(6.27857e6 * 2048), round(2.58946e4 * 1024)),
 }

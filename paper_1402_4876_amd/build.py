@@ -67,7 +67,10 @@ def resource_report(sources=None):
     """Per-kernel VGPRs, spills and occupancy from the compiler (gfx950).
 
     Returns a list of (kernel, vgprs, vgpr_spills, scratch_bytes_per_lane,
-    waves_per_simd); the fill kernels are meant to report zero spills.
+    waves_per_simd).  The plain fill kernels report no spills; the persistent
+    ones, which hold every class of their part under one register budget
+    and run one wave more than that budget fits, spill in their set-up and
+    walk (and a few reloads per step in some of their longest classes).
     """
     import re
     rows = []

@@ -1,6 +1,7 @@
 // Planning, bucketing, 2-bit packing and saturated-pair re-run kernels, and
 // the table of kernel entry points used by the host runtime.
 #include "dp_fill.h"
+#include "plan.h"
 
 namespace mica {
 
@@ -56,79 +57,100 @@ __device__ __forceinline__ bool int16_safe(int m, int n, int mode, int d0, int a
   return hi <= 32767 - 8 && lo >= -32767 + 8;
 }
 
-__global__ __launch_bounds__(256) void k_plan(const Params* __restrict__ prm) {
+__global__ __launch_bounds__(kPlanThreads) void k_plan(const Params* __restrict__ prm) {
   __shared__ uint32_t hist[kNumSubBuckets];
   for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < prm->n_pairs) {
-    const int m = prm->read_len[p], n = prm->win_len[p];
-    const int md = prm->mode ? (int)prm->mode[p] : prm->default_mode;
-    const uint64_t wo = prm->win_off[p], ro = prm->read_off[p];
-    const int h0 = md == 2 ? (prm->ext_h0 ? prm->ext_h0[p] : prm->ext_default_h0) : 0;
-    uint32_t st = 0;
-    if (m < prm->min_m || n < 0 || m > prm->max_m || n > prm->max_n || md < 0 || md > 2 || !((prm->mode_mask >> md) & 1) ||
-        h0 < 0 || h0 > kMaxH0)
-      st = kStLenLimit;
-    else if (wo > prm->ref_len || (uint64_t)n > prm->ref_len - wo) st = kStWinOob;
-    else if (ro > prm->reads_len || (uint64_t)m > prm->reads_len - ro) st = kStReadOob;
-    const bool want_start = (prm->flags & (kOutStart | kOutCigar)) != 0;
-    const bool want_cigar = (prm->flags & kOutCigar) != 0;
-    uint32_t b = kSkip;
-    if (st != 0 || m == 0 || n == 0) {
-      int score = 0, re = 0;
-      int ncig = 0;
-      // semi-global against an empty window: all insertions; an extension
-      // with an empty read or window: the anchor itself, or (empty window)
-      // all insertions when that is within the clipping penalty
-      const bool all_ins = st == 0 && m > 0 &&
-                           (md == 0 || (md == 2 && (long)prm->so + (long)m * prm->se <= (long)prm->ext_clip));
-      if (st == 0 && md == 2) score = h0;
-      if (all_ins) {
-        score = (md == 2 ? h0 : 0) - (prm->so + m * prm->se);
-        re = m;
-        ncig = 1;
-        if (want_cigar) {
-          if (prm->cigar_cap >= 1) prm->cigar[(size_t)p * prm->cigar_cap] = ((uint32_t)m << 4) | 1u;
-          else st |= kStCigarTrunc;
+  for (int rep = 0; rep < kPlanPairsPerThread; ++rep) {
+    const int64_t p = ((int64_t)blockIdx.x * kPlanPairsPerThread + rep) * blockDim.x + threadIdx.x;
+    if (p < prm->n_pairs) {
+      const int m = prm->read_len[p], n = prm->win_len[p];
+      const int md = prm->mode ? (int)prm->mode[p] : prm->default_mode;
+      const uint64_t wo = prm->win_off[p], ro = prm->read_off[p];
+      const int h0 = md == 2 ? (prm->ext_h0 ? prm->ext_h0[p] : prm->ext_default_h0) : 0;
+      uint32_t st = 0;
+      if (m < prm->min_m || n < 0 || m > prm->max_m || n > prm->max_n || md < 0 || md > 2 || !((prm->mode_mask >> md) & 1) ||
+          h0 < 0 || h0 > kMaxH0)
+        st = kStLenLimit;
+      else if (wo > prm->ref_len || (uint64_t)n > prm->ref_len - wo) st = kStWinOob;
+      else if (ro > prm->reads_len || (uint64_t)m > prm->reads_len - ro) st = kStReadOob;
+      const bool want_start = (prm->flags & (kOutStart | kOutCigar)) != 0;
+      const bool want_cigar = (prm->flags & kOutCigar) != 0;
+      uint32_t b = kSkip;
+      if (st != 0 || m == 0 || n == 0) {
+        int score = 0, re = 0;
+        int ncig = 0;
+        // semi-global against an empty window: all insertions; an extension
+        // with an empty read or window: the anchor itself, or (empty window)
+        // all insertions when that is within the clipping penalty
+        const bool all_ins = st == 0 && m > 0 &&
+                             (md == 0 || (md == 2 && (long)prm->so + (long)m * prm->se <= (long)prm->ext_clip));
+        if (st == 0 && md == 2) score = h0;
+        if (all_ins) {
+          score = (md == 2 ? h0 : 0) - (prm->so + m * prm->se);
+          re = m;
+          ncig = 1;
+          if (want_cigar) {
+            if (prm->cigar_cap >= 1) prm->cigar[(size_t)p * prm->cigar_cap] = ((uint32_t)m << 4) | 1u;
+            else st |= kStCigarTrunc;
+          }
         }
+        prm->score[p] = score;
+        prm->read_end[p] = re;
+        prm->ref_end[p] = 0;
+        if (want_start) {
+          prm->read_start[p] = 0;
+          prm->ref_start[p] = 0;
+        }
+        if (want_cigar) prm->n_cigar[p] = (st & kStCigarTrunc) ? -ncig : ncig;
+        prm->status[p] = st;
+      } else {
+        const int cls = prm->class_of_m[m];
+        const int d0 = class_lanes(cls) * class_rows(cls) - m;
+        int kind;
+        if (prm->flags & kForceInt32) kind = kK32;
+        else kind = int16_safe(m, n, md, d0, prm->sa, prm->sb, prm->so, prm->se, h0) ? kK16 : kK16Sat;
+        b = (uint32_t)(bucket_id(kind, cls, md) * kSubBins + sub_bin(cls, d0));
+        atomicAdd(&hist[b], 1u);
       }
-      prm->score[p] = score;
-      prm->read_end[p] = re;
-      prm->ref_end[p] = 0;
-      if (want_start) {
-        prm->read_start[p] = 0;
-        prm->ref_start[p] = 0;
-      }
-      if (want_cigar) prm->n_cigar[p] = (st & kStCigarTrunc) ? -ncig : ncig;
-      prm->status[p] = st;
-    } else {
-      const int cls = prm->class_of_m[m];
-      const int d0 = class_lanes(cls) * class_rows(cls) - m;
-      int kind;
-      if (prm->flags & kForceInt32) kind = kK32;
-      else kind = int16_safe(m, n, md, d0, prm->sa, prm->sb, prm->so, prm->se, h0) ? kK16 : kK16Sat;
-      b = (uint32_t)(bucket_id(kind, cls, md) * kSubBins + sub_bin(cls, d0));
-      atomicAdd(&hist[b], 1u);
+      prm->bucket_of[p] = b;
     }
-    prm->bucket_of[p] = b;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x)
     if (hist[i]) atomicAdd(&prm->scount[i], hist[i]);
 }
 
-// One block of kScanThreads: bucket sizes and starts, the start of every
-// (bucket, sub-bin) run inside its bucket, and the work-queue positions.
+// One block of kScanThreads, one thread per bucket and per queue position:
+// bucket sizes and starts, the start of every (bucket, sub-bin) run inside
+// its bucket, and the first work item of every queue position.
 constexpr int kScanThreads = 256;
 static_assert(kNumBuckets <= kScanThreads, "one thread per bucket");
+
+// exclusive prefix sum over the block (Hillis-Steele in LDS); *total gets the sum
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    const uint32_t x = t >= d ? sh[t - d] : 0u;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  const uint32_t incl = sh[t];
+  *total = sh[kScanThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan(const Params* __restrict__ prm) {
   __shared__ uint32_t cnt[kNumBuckets];
-  __shared__ uint32_t start[kNumBuckets];
+  __shared__ uint32_t sh[kScanThreads];
   const int b = threadIdx.x;
   uint32_t sub[kSubBins];
+  uint32_t acc = 0;
   if (b < kNumBuckets) {
-    uint32_t acc = 0;
 #pragma unroll
     for (int s = 0; s < kSubBins; ++s) {
       sub[s] = acc;
@@ -137,49 +159,57 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const Params* __restrict_
     cnt[b] = acc;
     prm->bcount[b] = acc;
   }
-  __syncthreads();
+  uint32_t n_sorted;
+  const uint32_t start = block_exclusive_scan(acc, sh, &n_sorted);  // also orders cnt[] before its reads
+  // queue position q = b serves bucket qorder[q]
+  uint32_t items = 0;
+  if (b < kNumBuckets) {
+    const int bq = (int)prm->qorder[b];
+    const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(bq), bucket_class(bq));
+    items = (cnt[bq] + ppi - 1) / ppi;
+  }
+  uint32_t n_items;
+  const uint32_t qs = block_exclusive_scan(items, sh, &n_items);
+  if (b < kNumBuckets) {
+    prm->qstart[b] = qs;
+    prm->bstart[b] = start;
+#pragma unroll
+    for (int s = 0; s < kSubBins; ++s) prm->sfill[b * kSubBins + s] = start + sub[s];
+  }
   if (b == 0) {
-    uint32_t acc = 0;
-    for (int i = 0; i < kNumBuckets; ++i) {
-      start[i] = acc;
-      acc += cnt[i];
-    }
-    uint32_t items = 0;
-    for (int q = 0; q < kNumBuckets; ++q) {
-      const int bq = (int)prm->qorder[q];
-      prm->qstart[q] = items;
-      const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(bq), bucket_class(bq));
-      items += (cnt[bq] + ppi - 1) / ppi;
-    }
-    prm->qstart[kNumBuckets] = items;
-    prm->counters[kCtrItems] = items;
+    prm->qstart[kNumBuckets] = n_items;
+    prm->counters[kCtrItems] = n_items;
     for (int q = 0; q < kPersistParts; ++q) prm->counters[kCtrQueueHead + q] = 0;
     prm->counters[kCtrRerun] = 0;
   }
-  __syncthreads();
-  if (b < kNumBuckets) {
-    prm->bstart[b] = start[b];
-#pragma unroll
-    for (int s = 0; s < kSubBins; ++s) prm->sfill[b * kSubBins + s] = start[b] + sub[s];
-  }
+  (void)n_sorted;
 }
 
-__global__ __launch_bounds__(256) void k_scatter(const Params* __restrict__ prm) {
+__global__ __launch_bounds__(kPlanThreads) void k_scatter(const Params* __restrict__ prm) {
   __shared__ uint32_t cnt[kNumSubBuckets];
   __shared__ uint32_t base[kNumSubBuckets];
   for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t b = kSkip, rank = 0;
-  if (p < prm->n_pairs) {
-    b = prm->bucket_of[p];
-    if (b != kSkip) rank = atomicAdd(&cnt[b], 1u);
+  uint32_t b[kPlanPairsPerThread], rank[kPlanPairsPerThread];
+#pragma unroll
+  for (int rep = 0; rep < kPlanPairsPerThread; ++rep) {
+    const int64_t p = ((int64_t)blockIdx.x * kPlanPairsPerThread + rep) * blockDim.x + threadIdx.x;
+    b[rep] = kSkip;
+    rank[rep] = 0;
+    if (p < prm->n_pairs) {
+      b[rep] = prm->bucket_of[p];
+      if (b[rep] != kSkip) rank[rep] = atomicAdd(&cnt[b[rep]], 1u);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x)
     base[i] = cnt[i] ? atomicAdd(&prm->sfill[i], cnt[i]) : 0;
   __syncthreads();
-  if (b != kSkip) prm->sorted[base[b] + rank] = (uint32_t)p;
+#pragma unroll
+  for (int rep = 0; rep < kPlanPairsPerThread; ++rep) {
+    const int64_t p = ((int64_t)blockIdx.x * kPlanPairsPerThread + rep) * blockDim.x + threadIdx.x;
+    if (b[rep] != kSkip) prm->sorted[base[b[rep]] + rank[rep]] = (uint32_t)p;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_pack2bit(const uint8_t* __restrict__ codes, int64_t n,

@@ -13,6 +13,7 @@
 #include "ctx.h"
 #include "dp_common.h"
 #include "mica_dp.h"
+#include "plan.h"
 
 using namespace mica;
 
@@ -478,12 +479,12 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   HIP_TRY(hipEventRecord(c->ev[rp], stream));
   c->ev_used[rp] = true;
 
-  const unsigned pblocks = (unsigned)((b->n_pairs + 255) / 256);
+  const unsigned pblocks = (unsigned)((b->n_pairs + kPlanPairsPerBlock - 1) / kPlanPairsPerBlock);
   std::vector<Launch> seq;
   seq.push_back({K.zero, 1, 256, 0, false});
-  seq.push_back({K.plan, pblocks, 256, 0, false});
+  seq.push_back({K.plan, pblocks, kPlanThreads, 0, false});
   seq.push_back({K.scan, 1, 256, 0, false});
-  seq.push_back({K.scatter, pblocks, 256, 0, false});
+  seq.push_back({K.scatter, pblocks, kPlanThreads, 0, false});
   for (size_t i = 0; i < fills.size(); ++i) {
     // each fill kernel gets the blocks it keeps resident (its waves index
     // the first slots of the scratch)
