@@ -67,10 +67,11 @@ def resource_report(sources=None):
     """Per-kernel VGPRs, spills and occupancy from the compiler (gfx950).
 
     Returns a list of (kernel, vgprs, vgpr_spills, scratch_bytes_per_lane,
-    waves_per_simd).  The plain fill kernels report no spills; the persistent
-    ones, which hold every class of their part under one register budget
-    and run one wave more than that budget fits, spill in their set-up and
-    walk (and a few reloads per step in some of their longest classes).
+    waves_per_simd).  Kernels compiled for one wave more than their
+    spill-free budget (see fill_waves and persist_waves) spill in their
+    set-up and walk; the step loops of the plain fill kernels do not spill,
+    those of a few of the persistent kernels' longest classes reload a value
+    or three per step.
     """
     import re
     rows = []
