@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <charconv>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -17,6 +18,10 @@
 #include <string>
 #include <thread>
 #include <vector>
+
+#include <sys/mman.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "ctx.h"
 #include "fm_common.h"
@@ -141,7 +146,11 @@ __global__ void k_pick(int64_t n, const int32_t* __restrict__ len, const int32_t
 
 struct HostBatch {
   int64_t n = 0;
-  std::string text;  // names, sequences and qualities of the batch
+  // names, sequences and qualities of the batch: offsets into the mapped
+  // input file (mapped != nullptr), else into text, a copy of the lines
+  const char* mapped = nullptr;
+  std::string text;
+  const char* base() const { return mapped ? mapped : text.data(); }
   std::vector<uint64_t> name_off, seq_off, qual_off;
   std::vector<int32_t> name_len, len;
   std::vector<uint8_t> non_acgt;
@@ -173,15 +182,50 @@ struct Queue {
   }
 };
 
-// buffered FASTQ reader: whole lines out of large reads of the file
+// FASTQ reader: whole lines of the file.  A regular file is mapped into
+// memory and its lines are handed out in place (batches keep offsets into
+// the mapping, which lives until the reader is destroyed: after every batch
+// is written); anything else (a pipe) is read through a buffer, whose lines
+// the batch copies.
 struct LineReader {
   FILE* f = nullptr;
   std::vector<char> buf;
   size_t beg = 0, end = 0;
   bool eof = false;
-  explicit LineReader(FILE* fp) : f(fp), buf(size_t(16) << 20) {}
-  // next line without its newline; false at the end of the file
+  const char* map = nullptr;
+  size_t map_len = 0;
+  explicit LineReader(FILE* fp) : f(fp) {
+    struct stat st;
+    const int fd = fileno(fp);
+    if (fd >= 0 && fstat(fd, &st) == 0 && S_ISREG(st.st_mode) && st.st_size > 0) {
+      void* m = mmap(nullptr, (size_t)st.st_size, PROT_READ, MAP_PRIVATE, fd, 0);
+      if (m != MAP_FAILED) {
+        map = (const char*)m;
+        map_len = (size_t)st.st_size;
+        (void)madvise(m, map_len, MADV_SEQUENTIAL);
+        return;
+      }
+    }
+    buf.resize(size_t(16) << 20);
+  }
+  ~LineReader() {
+    if (map) (void)munmap((void*)map, map_len);
+  }
+  LineReader(const LineReader&) = delete;
+  LineReader& operator=(const LineReader&) = delete;
+  // next line without its newline (nor a carriage return before it); false
+  // at the end of the file
   bool next(const char** s, size_t* n) {
+    if (map) {
+      if (beg >= map_len) return false;
+      const char* nl = (const char*)memchr(map + beg, '\n', map_len - beg);
+      const size_t e = nl ? (size_t)(nl - map) : map_len;
+      *s = map + beg;
+      *n = e - beg;
+      beg = nl ? e + 1 : map_len;
+      if (*n && (*s)[*n - 1] == '\r') --*n;
+      return true;
+    }
     for (;;) {
       char* nl = (char*)memchr(buf.data() + beg, '\n', end - beg);
       if (nl) {
@@ -367,6 +411,19 @@ mica_status_t ensure_words(Slot& s, size_t words) {
 // packing on `threads` threads); *bad set for malformed input
 std::unique_ptr<HostBatch> parse_batch(LineReader& in, int64_t max_reads, int threads, bool* bad) {
   auto b = std::make_unique<HostBatch>();
+  b->mapped = in.map;
+  b->name_off.reserve((size_t)max_reads);
+  b->seq_off.reserve((size_t)max_reads);
+  b->qual_off.reserve((size_t)max_reads);
+  b->name_len.reserve((size_t)max_reads);
+  b->len.reserve((size_t)max_reads);
+  // offset of a line: in place in the mapping, else appended to the copy
+  auto keep = [&](const char* p, size_t len) -> uint64_t {
+    if (in.map) return (uint64_t)(p - in.map);
+    const uint64_t o = b->text.size();
+    b->text.append(p, len);
+    return o;
+  };
   const char* s;
   size_t n;
   while (b->n < max_reads) {
@@ -378,18 +435,16 @@ std::unique_ptr<HostBatch> parse_batch(LineReader& in, int64_t max_reads, int th
     }
     size_t nl = 1;
     while (nl < n && s[nl] != ' ' && s[nl] != '\t') ++nl;
-    b->name_off.push_back(b->text.size());
+    b->name_off.push_back(keep(s + 1, nl - 1));
     b->name_len.push_back((int32_t)(nl - 1));
-    b->text.append(s + 1, nl - 1);
     const char* q;
     size_t qn;
     if (!in.next(&q, &qn)) {
       *bad = true;
       return b;
     }
-    b->seq_off.push_back(b->text.size());
+    b->seq_off.push_back(keep(q, qn));
     b->len.push_back((int32_t)qn);
-    b->text.append(q, qn);
     if (!in.next(&q, &qn) || qn == 0 || q[0] != '+') {
       *bad = true;
       return b;
@@ -398,8 +453,7 @@ std::unique_ptr<HostBatch> parse_batch(LineReader& in, int64_t max_reads, int th
       *bad = true;
       return b;
     }
-    b->qual_off.push_back(b->text.size());
-    b->text.append(q, qn);
+    b->qual_off.push_back(keep(q, qn));
     b->n++;
   }
   // 2-bit packing, each read from a 16-base boundary
@@ -416,7 +470,7 @@ std::unique_ptr<HostBatch> parse_batch(LineReader& in, int64_t max_reads, int th
   auto pack = [&](int th, int64_t lo, int64_t hi) {
     int32_t mx = 0;
     for (int64_t r = lo; r < hi; ++r) {
-      const char* sq = b->text.data() + b->seq_off[r];
+      const char* sq = b->base() + b->seq_off[r];
       const int m = b->len[r];
       uint32_t* w = b->words.data() + b->roff[r] / 16;
       bool ok = true;
@@ -527,6 +581,13 @@ mica_status_t enqueue_batch(mica_pipe* P, Slot& s, const HostBatch& b) {
 inline uint32_t ref_base(const mica_pipe* P, uint64_t p) { return (P->ref_words[p >> 4] >> (2 * (p & 15))) & 3u; }
 
 // SAM records of reads [lo, hi) of a finished batch
+// decimal text of v appended to out
+inline void append_int(std::string* out, long long v) {
+  char buf[24];
+  const auto r = std::to_chars(buf, buf + sizeof(buf), v);
+  out->append(buf, (size_t)(r.ptr - buf));
+}
+
 void format_range(const mica_pipe* P, const HostBatch& b, const char* res, const uint32_t* cig, int64_t lo,
                   int64_t hi, std::string* out) {
   const ResLayout lay(b.n);
@@ -537,21 +598,23 @@ void format_range(const mica_pipe* P, const HostBatch& b, const char* res, const
   const int32_t* mapq = (const int32_t*)(res + lay.mapq);
   const int32_t* ncig = (const int32_t*)(res + lay.ncig);
   const int32_t* coff = (const int32_t*)(res + lay.cig_off);
-  char tmp[64];
   for (int64_t r = lo; r < hi; ++r) {
-    const char* T = b.text.data();
+    const char* T = b.base();
     out->append(T + b.name_off[r], (size_t)b.name_len[r]);
     const int m = b.len[r];
     const int k_ = b.non_acgt[r] ? kUnmapped : kind[r];
     if (k_ == kBySearch || k_ == kByDp) {
       out->append("\t0\t");
       out->append(P->ref_name);
-      snprintf(tmp, sizeof(tmp), "\t%lld\t%d\t", (long long)pos[r] + 1, mapq[r]);
-      out->append(tmp);
+      out->push_back('\t');
+      append_int(out, (long long)pos[r] + 1);
+      out->push_back('\t');
+      append_int(out, mapq[r]);
+      out->push_back('\t');
       int nm = 0;
       if (k_ == kBySearch) {
-        snprintf(tmp, sizeof(tmp), "%dM", m);
-        out->append(tmp);
+        append_int(out, m);
+        out->push_back('M');
         nm = mm[r];
       } else {
         // NM: mismatches in M runs plus inserted and deleted bases
@@ -561,8 +624,8 @@ void format_range(const mica_pipe* P, const HostBatch& b, const char* res, const
         for (int x = 0; x < ncig[r]; ++x) {
           const uint32_t w = cig[coff[r] + x];
           const int L = (int)(w >> 4), op = (int)(w & 15);
-          snprintf(tmp, sizeof(tmp), "%d%c", L, op == 0 ? 'M' : (op == 1 ? 'I' : 'D'));
-          out->append(tmp);
+          append_int(out, L);
+          out->push_back(op == 0 ? 'M' : (op == 1 ? 'I' : 'D'));
           if (op == 0) {
             for (int t = 0; t < L; ++t) nm += (uint32_t)code_of(sq[qp + t]) != ref_base(P, rp + t);
             qp += L;
@@ -580,8 +643,11 @@ void format_range(const mica_pipe* P, const HostBatch& b, const char* res, const
       out->append(T + b.seq_off[r], (size_t)m);
       out->push_back('\t');
       out->append(T + b.qual_off[r], (size_t)m);
-      snprintf(tmp, sizeof(tmp), "\tNM:i:%d\tAS:i:%d\n", nm, score[r]);
-      out->append(tmp);
+      out->append("\tNM:i:");
+      append_int(out, nm);
+      out->append("\tAS:i:");
+      append_int(out, score[r]);
+      out->push_back('\n');
     } else {
       out->append("\t4\t*\t0\t0\t*\t*\t0\t0\t");
       if (m == 0) {
@@ -659,6 +725,12 @@ extern "C" mica_status_t mica_pipe_run(mica_pipe_t P, const char* fastq_path, co
                     "\n@PG\tID:mica-mi355x\tPN:mica-mi355x\n";
     fwrite(h.data(), 1, h.size(), fout);
   }
+  // A seekable SAM file takes each batch's formatted parts with one pwrite
+  // per format thread at their offsets (the copies into the page cache run
+  // in parallel); anything else (a pipe) takes them in order through fout.
+  int64_t wpos = -1;
+  if (fflush(fout) == 0) wpos = (int64_t)ftello(fout);
+  const bool positional = wpos >= 0 && lseek(fileno(fout), 0, SEEK_CUR) >= 0;
   mica_pipe_stats_t S;
   std::memset(&S, 0, sizeof(S));
   std::atomic<int> err_status{MICA_OK};
@@ -680,10 +752,11 @@ extern "C" mica_status_t mica_pipe_run(mica_pipe_t P, const char* fastq_path, co
   Queue<Done> gpu_done;
   gpu_done.cap = 2;
 
-  // reader
+  // reader (the mapping of the input lives until this function returns,
+  // after the writer has formatted every batch)
+  LineReader in(fin);
   double parse_s = 0;
   std::thread reader([&] {
-    LineReader in(fin);
     for (;;) {
       const auto tp = std::chrono::steady_clock::now();
       bool bad = false;
@@ -705,6 +778,9 @@ extern "C" mica_status_t mica_pipe_run(mica_pipe_t P, const char* fastq_path, co
   // writer
   double fmt_s = 0, gpu_s = 0;
   std::thread writer([&] {
+    // formatted SAM text per format thread, kept across batches so that
+    // their memory is reused instead of faulted in again for every batch
+    std::vector<std::string> parts((size_t)P->prm.format_threads);
     for (;;) {
       Done d = gpu_done.pop();
       if (!d.b) return;
@@ -722,7 +798,7 @@ extern "C" mica_status_t mica_pipe_run(mica_pipe_t P, const char* fastq_path, co
           set_err(MICA_ERR_HIP, "CIGAR copy failed");
         } else {
           const int T = P->prm.format_threads;
-          std::vector<std::string> parts((size_t)T);
+          for (auto& x : parts) x.clear();
           std::vector<std::thread> th;
           const int64_t chunk = (b.n + T - 1) / T;
           for (int t = 0; t < T; ++t) {
@@ -733,8 +809,33 @@ extern "C" mica_status_t mica_pipe_run(mica_pipe_t P, const char* fastq_path, co
             });
           }
           for (auto& x : th) x.join();
-          for (auto& x : parts)
-            if (fwrite(x.data(), 1, x.size(), fout) != x.size()) set_err(MICA_ERR_INVALID_ARG, "SAM write failed");
+          if (positional) {
+            std::vector<int64_t> at((size_t)T);
+            for (int t = 0; t < T; ++t) {
+              at[(size_t)t] = wpos;
+              wpos += (int64_t)parts[(size_t)t].size();
+            }
+            std::atomic<bool> ok{true};
+            th.clear();
+            for (int t = 0; t < T; ++t)
+              th.emplace_back([&, t] {
+                const std::string& x = parts[(size_t)t];
+                size_t done = 0;
+                while (done < x.size()) {
+                  const ssize_t w = pwrite(fileno(fout), x.data() + done, x.size() - done, (off_t)(at[(size_t)t] + (int64_t)done));
+                  if (w <= 0) {
+                    ok = false;
+                    return;
+                  }
+                  done += (size_t)w;
+                }
+              });
+            for (auto& x : th) x.join();
+            if (!ok) set_err(MICA_ERR_INVALID_ARG, "SAM write failed");
+          } else {
+            for (auto& x : parts)
+              if (fwrite(x.data(), 1, x.size(), fout) != x.size()) set_err(MICA_ERR_INVALID_ARG, "SAM write failed");
+          }
           const int32_t* kind = (const int32_t*)((const char*)s.h_res + lay.kind);
           for (int64_t r = 0; r < b.n; ++r) {
             const int k_ = b.non_acgt[r] ? kUnmapped : kind[r];

@@ -8,6 +8,7 @@ pipeline's stated rules (include/mica_pipe.h); every SAM field must match.
 Batches are small so that a file spans several batches on both slots.
 """
 import os
+import threading
 
 import numpy as np
 import pytest
@@ -236,3 +237,59 @@ def test_pipeline_input_forms(tmp_path):
     assert len(outs["low"]) == len(outs["plain"])
     for a, b in zip(outs["plain"], outs["low"]):
         assert a[:9] == b[:9] and a[10:] == b[10:] and a[9].lower() == b[9]
+
+
+def test_pipeline_reads_from_a_pipe(tmp_path):
+    """A FIFO (read through the buffered reader, not mapped) gives the same
+    SAM records as the regular file (mapped in place)."""
+    import paper_1402_4876_amd as mica
+    ref = _reference()
+    recs = _records(ref, n=900, seed=15)
+    plain = tmp_path / "plain.fq"
+    _write_fastq(plain, recs)
+    fifo = tmp_path / "reads.fifo"
+    os.mkfifo(fifo)
+    data = plain.read_bytes()
+
+    def feed():
+        with open(fifo, "wb") as f:
+            f.write(data)
+
+    pipe = mica.Pipeline(pack_codes(ref), len(ref), "chrT", batch_reads=300, format_threads=2)
+    pipe.run(plain, tmp_path / "plain.sam")
+    t = threading.Thread(target=feed, daemon=True)
+    t.start()
+    st = pipe.run(fifo, tmp_path / "fifo.sam")
+    t.join(timeout=30)
+    pipe.close()
+    assert not t.is_alive()
+    a = open(tmp_path / "plain.sam").read()
+    b = open(tmp_path / "fifo.sam").read()
+    assert st["reads"] == len(recs) and a == b
+
+
+def test_pipeline_writes_to_a_pipe(tmp_path):
+    """SAM written into a FIFO (in order through the stream, not by
+    positional writes) equals the SAM written into a regular file."""
+    import paper_1402_4876_amd as mica
+    ref = _reference()
+    recs = _records(ref, n=900, seed=16)
+    fq = tmp_path / "reads.fq"
+    _write_fastq(fq, recs)
+    fifo = tmp_path / "out.fifo"
+    os.mkfifo(fifo)
+    got = []
+
+    def drain():
+        with open(fifo, "rb") as f:
+            got.append(f.read())
+
+    pipe = mica.Pipeline(pack_codes(ref), len(ref), "chrT", batch_reads=300, format_threads=3)
+    pipe.run(fq, tmp_path / "plain.sam")
+    t = threading.Thread(target=drain, daemon=True)
+    t.start()
+    st = pipe.run(fq, fifo)
+    t.join(timeout=30)
+    pipe.close()
+    assert not t.is_alive() and st["reads"] == len(recs)
+    assert got[0] == (tmp_path / "plain.sam").read_bytes()
