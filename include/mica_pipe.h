@@ -71,9 +71,10 @@ mica_status_t mica_pipe_create(int hip_device, const uint32_t *host_ref2b, uint6
 /* Align every record of the FASTQ file and write SAM (header and one record
  * per read, in input order).  Either path may name a pipe: a regular input
  * file is mapped into memory for the run (it must not change meanwhile), a
- * regular output file is written at computed offsets, a pipe in order.  Returns MICA_ERR_INVALID_ARG for unreadable or
- * malformed input (no output is promised then); the pipeline stays usable.
- * One run at a time per pipeline: the slots and contexts are its own. */
+ * regular output file is written at computed offsets, a pipe in order.
+ * Returns MICA_ERR_INVALID_ARG for unreadable or malformed input (no output
+ * is promised then); the pipeline stays usable.  One run at a time per
+ * pipeline: the slots and contexts are its own. */
 mica_status_t mica_pipe_run(mica_pipe_t pipe, const char *fastq_path, const char *sam_path,
                             mica_pipe_stats_t *stats);
 
