@@ -44,10 +44,10 @@ KERNEL_SOURCES = ("dp_fill.h", "dp_common.h")
 MEASURED_TRAFFIC = {
     # config: (kernel source sha256, fetch bytes, write bytes); for the
     # extension workload the sums over its fill launches and re-run
-    "c1": ("80fd2284a5cc0f2ce40123c912a0be2ee6da4bc4dd0121753cab0f787d68ceed",
-           round(1.10853e7 * 2048), round(5.20372e7 * 1024)),
-    "ext": ("80fd2284a5cc0f2ce40123c912a0be2ee6da4bc4dd0121753cab0f787d68ceed",
-            round(4.40155e6 * 2048), round(9.70931e6 * 1024)),
+    "c1": ("a16655631df62fbeb9c702df7398e12cfa09f7d529f8883292d3d3d79609c106",
+           round(1.10724e7 * 2048), round(5.20371e7 * 1024)),
+    "ext": ("a16655631df62fbeb9c702df7398e12cfa09f7d529f8883292d3d3d79609c106",
+            round(4.42975e6 * 2048), round(9.7082e6 * 1024)),
     # the search kernel, keyed by its own sources (fm_search.hip, fm_common.h)
     "bwt": ("e51dba48c50b365e3927de4f770d2699994e5edfa1a080f0baae8ed9022d5f76", round(6.27857e6 * 2048), round(2.58946e4 * 1024)),
 }

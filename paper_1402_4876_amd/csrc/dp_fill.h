@@ -711,9 +711,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         };
         // a diagonal run is examined C cells per lane, X*C <= 64 at a time
         // (measured: 64 cells pay off on the long diagonals of semi-global
-        // reads; local and extension walks, with more turns, do as well with
-        // 32 or fewer)
-        constexpr int C = MODE == 0 ? 64 / X : (X <= 16 ? 4 : (X == 32 ? 2 : 1));
+        // reads and, by 1%, of extensions; local walks, with more turns and
+        // a prefix sum per cell for the zero test, do as well with 32 or
+        // fewer)
+        constexpr int C = MODE != 1 ? 64 / X : (X <= 16 ? 4 : (X == 32 ? 2 : 1));
         constexpr int XC = X * C;
         constexpr uint64_t xcmask = XC == 64 ? ~0ull : ((1ull << (XC == 64 ? 0 : XC)) - 1);
         auto first_clear_xc = [&](uint64_t msk) -> int {
