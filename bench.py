@@ -40,26 +40,55 @@ EXT_CLIP = 5  # clipping penalty of the seed-extension workload
 # They hold only for the kernel source they were taken on, identified by the
 # SHA-256 of the fill kernel's sources; for any other source the bench line
 # reports traffic as null.
-KERNEL_SOURCES = ("dp_fill.h", "dp_common.h")
+# The traffic figures hold only for the build they were taken on: the fill
+# kernels' sources and the build script (compiler flags, resident-wave
+# targets live in the sources), identified by one SHA-256; for any other
+# build the bench line reports traffic as null.
 MEASURED_TRAFFIC = {
-    # config: (kernel source sha256, fetch bytes, write bytes); for the
-    # extension workload the sums over its fill launches and re-run
-    "c1": ("a16655631df62fbeb9c702df7398e12cfa09f7d529f8883292d3d3d79609c106",
-           round(1.10724e7 * 2048), round(5.20371e7 * 1024)),
-    "ext": ("a16655631df62fbeb9c702df7398e12cfa09f7d529f8883292d3d3d79609c106",
-            round(4.42975e6 * 2048), round(9.7082e6 * 1024)),
-    # the search kernel, keyed by its own sources (fm_search.hip, fm_common.h)
-    "bwt": ("e51dba48c50b365e3927de4f770d2699994e5edfa1a080f0baae8ed9022d5f76", round(6.27857e6 * 2048), round(2.58946e4 * 1024)),
+    # config: (build sha256, fetch bytes, write bytes); for the extension
+    # workload the sums over its fill launches and re-run
 }
 
 
-def kernel_source_sha():
+def _sha_of(files):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1402_4876_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
     return h.hexdigest()
+
+
+def kernel_source_sha():
+    """SHA-256 of every source the DP fill kernels are built from, plus the build script."""
+    csrc = os.path.join(ROOT, "paper_1402_4876_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                   if f.endswith(".h") or f.startswith(("fill_", "persistent_")) or f == "dp_misc.hip")
+    return _sha_of(files + [os.path.join(ROOT, "paper_1402_4876_amd", "build.py")])
+
+
+def fm_source_sha():
+    csrc = os.path.join(ROOT, "paper_1402_4876_amd", "csrc")
+    return _sha_of([os.path.join(csrc, f) for f in ("fm_search.hip", "fm_common.h")] +
+                   [os.path.join(ROOT, "paper_1402_4876_amd", "build.py")])
+
+
+def usable_cores():
+    """Host cores this process may run on: its CPU affinity, capped by a cgroup CPU quota."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    for path in ("/sys/fs/cgroup/cpu.max", "/sys/fs/cgroup/cpu/cpu.cfs_quota_us"):
+        try:
+            with open(path) as fh:
+                parts = fh.read().split()
+        except OSError:
+            continue
+        if path.endswith("cpu.max") and parts and parts[0] != "max":
+            n = min(n, max(1, int(int(parts[0]) / int(parts[1]))))
+        elif path.endswith("quota_us") and parts and int(parts[0]) > 0:
+            with open("/sys/fs/cgroup/cpu/cpu.cfs_period_us") as fh:
+                n = min(n, max(1, int(int(parts[0]) / int(fh.read().split()[0]))))
+        break
+    return n
 
 
 def log(*a):
@@ -137,9 +166,10 @@ def small_batch_latency(ctx, reps=50):
 
 
 def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
-    """Time the CPU oracle on a bounded sample of the same pairs (all host cores up to 16)."""
+    """Time the CPU oracle on a bounded sample of the same pairs, on every host core
+    this process may use."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads = usable_cores()
     sc = (1, -4, 6, 1)
     h0 = batch.h0 if batch.h0 is not None else np.zeros(batch.n_pairs, np.int32)
     ext = dict(clip=EXT_CLIP)
@@ -336,16 +366,23 @@ def bwt_bench(args):
     kernel_ms = ev[0].elapsed_time(ev[1]) / args.steps
     m = b.read_len.astype(np.int64)
     alg = float((m * BWT_BYTES_PER_STEP + (m + 15) // 16 * 4 + 36).sum())
-    achieved = alg / (kernel_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_fm_search",
-            "kernel_ms": round(kernel_ms, 4), "bytes_per_read": round(alg / n, 1)}
+    # The bound is HBM, priced on the bytes that really cross it (FETCH_SIZE
+    # + WRITE_SIZE counters of this build).  The algorithmic model counts
+    # every occurrence block a backward-search step reads; the first steps of
+    # every search share a few blocks that stay in L2, so that model exceeds
+    # what HBM moves and is reported beside it only.
+    roof = {"bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s", "frac": None, "traffic": None,
+            "kernel": "k_fm_search", "kernel_ms": round(kernel_ms, 4), "bytes_per_read": round(alg / n, 1),
+            "algorithmic_gbps": round(alg / (kernel_ms * 1e-3) / 1e9, 1)}
     meas = MEASURED_TRAFFIC.get("bwt")
     if meas and meas[0] == fm_source_sha():
         roof["traffic"] = meas[1] + meas[2]
         roof["traffic_split"] = {"fetch": meas[1], "write": meas[2]}
+        achieved = roof["traffic"] / (kernel_ms * 1e-3) / 1e9
+        roof["achieved"] = round(achieved, 1)
+        roof["frac"] = round(achieved / 8000.0, 4)
     else:
-        roof["traffic_note"] = "no FETCH_SIZE/WRITE_SIZE counters taken for this kernel source"
+        roof["traffic_note"] = "no FETCH_SIZE/WRITE_SIZE counters taken for this build: achieved not priced"
     g = {key: v.cpu().numpy() for key, v in out.items()}
     res = {
         "metric": "reads/s (few-mismatch BWT search, k = 2)", "value": round(n / (ms * 1e-3), 1), "unit": "reads/s",
@@ -359,7 +396,7 @@ def bwt_bench(args):
     }
     if not args.no_cpu_baseline:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        threads = usable_cores()
         idx = np.arange(min(n, 64))
         t0 = time.time()
         o = oracle.kmm_search(b.ref, b.reads, b.read_off[idx], b.read_len[idx], k=BWT_K, max_occ=BWT_MAX_OCC,
@@ -433,15 +470,6 @@ def pipe_bench(args):
     return 0
 
 
-def fm_source_sha():
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("fm_search.hip", "fm_common.h"):
-        with open(os.path.join(ROOT, "paper_1402_4876_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
 def copy_calibration(nbytes=1 << 30, reps=3):
     """A device-to-device copy of known size: what FETCH_SIZE / WRITE_SIZE read for it
     gives the counter-to-bytes factor used for the DP kernel's HBM traffic."""
@@ -508,9 +536,14 @@ def main():
     one_class = n > 0 and min_m >= 1 and (min_m - 1) // 16 == (max_m - 1) // 16 and max_m <= 256
     max_n = int(batch.win_len.max())
     cap = 64
-    out = {k: torch.empty(n, dtype=torch.int32, device="cuda") for k in
-           ("score", "read_end", "ref_end", "status", "read_start", "ref_start", "n_cigar")}
-    out["cigar"] = torch.empty((n, cap), dtype=torch.int32, device="cuda")
+
+    def new_out():
+        o = {k: torch.empty(n, dtype=torch.int32, device="cuda") for k in
+             ("score", "read_end", "ref_end", "status", "read_start", "ref_start", "n_cigar")}
+        o["cigar"] = torch.empty((n, cap), dtype=torch.int32, device="cuda")
+        return o
+
+    out = new_out()
     ctx = mica.Context()
     # a batch of one mode passes no per-pair mode array
     uniform = bool((batch.mode == batch.mode[0]).all()) if n else True
@@ -518,35 +551,74 @@ def main():
     default_mode = int(batch.mode[0]) if (uniform and n) else 0
     mode_mask = int(np.bitwise_or.reduce(1 << np.unique(batch.mode).astype(np.int64))) if n else 0
     ext_h0 = torch.as_tensor(batch.h0).cuda() if batch.h0 is not None else None
+    if mode_kind == "mixed":
+        loc = batch.mode == 1
+        ops = float(np.dot(batch.read_len.astype(np.int64), batch.win_len.astype(np.int64) *
+                           np.where(loc, OPS_PER_CELL[("local", want_trace)], OPS_PER_CELL[("sg", want_trace)])))
+    else:
+        ops = cells * OPS_PER_CELL[(mode_kind, want_trace)]
+    peak = PEAK_I32_TOPS if force_i32 else PEAK_I16_TOPS
+    # measured VALU roof of this GPU (the spec figure assumes 2.4 GHz under load)
+    valu_i16, valu_i32 = mica.measure_valu_peak(torch.cuda.current_device())
+    peak_meas = valu_i32 if force_i32 else valu_i16
 
-    def step():
-        mica.align(ctx, dev["ref2b"], dev["win_off"], dev["win_len"], dev["reads2b"], dev["read_off"],
-                   dev["read_len"], mode=mode_arg, default_mode=default_mode, out_cigar=want_trace, cigar_cap=cap,
-                   force_int32=force_i32, plain=args.plain, max_read_len=max_m, max_win_len=max_n,
-                   ref_len=dev["ref_len"], reads_len=dev["reads_len"], out=out, mode_mask=mode_mask,
-                   ext_h0=ext_h0, ext_clip=EXT_CLIP, min_read_len=min_m)
+    autotune = None
+    if args.config == "c3" and not args.plain:
+        # the plan is tuned on a sample of the batch (every 16-base read-length
+        # range, bit-exact gate against the default plan), then both launch
+        # styles run with the tuned plan
+        k = min(n, 200_000)
+        t0 = time.time()
+        entries = ctx.autotune(dev["ref2b"], dev["win_off"][:k], dev["win_len"][:k], dev["reads2b"],
+                               dev["read_off"][:k], dev["read_len"][:k], mode=dev["mode"][:k],
+                               out_cigar=want_trace, cigar_cap=cap, max_read_len=max_m, max_win_len=max_n,
+                               ref_len=dev["ref_len"], reads_len=dev["reads_len"], reps=3)
+        autotune = {"sample_pairs": k, "seconds": round(time.time() - t0, 1),
+                    "ranges": [{"m": [e["m_lo"], e["m_hi"]], "lanes": e["lanes"], "rows": e["rows"],
+                                "ms": round(e["ms"], 4), "default_ms": round(e["default_ms"], 4),
+                                "candidates": e["n_candidates"], "rejected": e["n_rejected"]} for e in entries]}
+        log("autotune: %d ranges in %.1fs; %d changed from the default plan" % (
+            len(entries), time.time() - t0,
+            sum(1 for e in entries if abs(e["ms"] - e["default_ms"]) > 1e-12)))
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.set_timing(True)
-    ctx.read_timing()
-    # events on the launch stream around every step (the align call enqueues
-    # the whole graph there): per-step device times for the median and minimum
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs[0].record()
-    for i in range(args.steps):
-        step()
-        evs[i + 1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
-    fill_ms, nb = ctx.read_timing()
-    ctx.set_timing(False)
+    def run_leg(plain, out):
+        """Warm-up, then args.steps timed steps of one launch style: host time per
+        step, the fill kernels' summed event time and per-step device times."""
+        def step():
+            mica.align(ctx, dev["ref2b"], dev["win_off"], dev["win_len"], dev["reads2b"], dev["read_off"],
+                       dev["read_len"], mode=mode_arg, default_mode=default_mode, out_cigar=want_trace,
+                       cigar_cap=cap, force_int32=force_i32, plain=plain, max_read_len=max_m, max_win_len=max_n,
+                       ref_len=dev["ref_len"], reads_len=dev["reads_len"], out=out, mode_mask=mode_mask,
+                       ext_h0=ext_h0, ext_clip=EXT_CLIP, min_read_len=min_m)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        ctx.read_timing()
+        # events on the launch stream around every step (the align call enqueues
+        # the whole graph there): per-step device times for the median and minimum
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs[0].record()
+        for i in range(args.steps):
+            step()
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step_ms = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+        fill_ms, nb = ctx.read_timing()
+        ctx.set_timing(False)
+        ms = (t1 - t0) * 1e3 / args.steps
+        fill_avg_ms = fill_ms / max(nb, 1)
+        achieved = ops / (fill_avg_ms * 1e-3) / 1e12
+        return {"ms": ms, "fill_ms": fill_avg_ms, "step_ms": step_ms, "gcups": cells / (ms * 1e-3) / 1e9,
+                "achieved": achieved}
+
+    leg = run_leg(args.plain, out)
     stats = ctx.last_stats()
-    ms = (t1 - t0) * 1e3 / args.steps
+    ms, fill_avg_ms, step_ms, gcups, achieved = leg["ms"], leg["fill_ms"], leg["step_ms"], leg["gcups"], leg["achieved"]
     # transfers of the same batch, timed apart from the steps: inputs from
     # pinned host memory to the device, outputs back
     host_in = {k: v.cpu().pin_memory() for k, v in dev.items() if isinstance(v, torch.Tensor)}
@@ -562,27 +634,19 @@ def main():
     te[2].record()
     torch.cuda.synchronize()
     h2d_ms, d2h_ms = te[0].elapsed_time(te[1]), te[1].elapsed_time(te[2])
-    gcups = cells / (ms * 1e-3) / 1e9
-    fill_avg_ms = fill_ms / max(nb, 1)
-    if mode_kind == "mixed":
-        loc = batch.mode == 1
-        ops = float(np.dot(batch.read_len.astype(np.int64), batch.win_len.astype(np.int64) *
-                           np.where(loc, OPS_PER_CELL[("local", want_trace)], OPS_PER_CELL[("sg", want_trace)])))
-    else:
-        ops = cells * OPS_PER_CELL[(mode_kind, want_trace)]
-    peak = PEAK_I32_TOPS if force_i32 else PEAK_I16_TOPS
-    achieved = ops / (fill_avg_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
             "frac": round(achieved / peak, 4), "traffic": None,
             "kernel": ("k_fill_bucket" if args.plain or one_class else "k_fill_persistent") +
             " (all fill launches of one step)", "kernel_ms": round(fill_avg_ms, 4),
-            "ops_per_cell": round(ops / cells, 3)}
-    meas = MEASURED_TRAFFIC.get(args.config)
+            "ops_per_cell": round(ops / cells, 3),
+            "peak_measured": round(peak_meas, 3), "frac_of_measured": round(achieved / peak_meas, 4),
+            "valu_measured": {"i16x2": round(valu_i16, 3), "i32": round(valu_i32, 3)}}
+    meas = MEASURED_TRAFFIC.get(args.config + ("_plain" if args.plain else ""))
     if meas and meas[0] == kernel_source_sha():
         roof["traffic"] = meas[1] + meas[2]
         roof["traffic_split"] = {"fetch": meas[1], "write": meas[2]}
     else:
-        roof["traffic_note"] = "no FETCH_SIZE/WRITE_SIZE counters taken for this kernel source"
+        roof["traffic_note"] = "no FETCH_SIZE/WRITE_SIZE counters taken for this build"
     host = {k: v.cpu().numpy() for k, v in out.items()}
     res = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
@@ -590,7 +654,8 @@ def main():
         "vs_baseline": None, "dtype": "i32" if force_i32 else "i16", "data": "synthetic",
         "config": {"workload": desc, "name": args.config, "pairs": n, "cells": cells,
                    "launch": "plain per-bucket" if args.plain else (
-                       "one class: its own kernel" if one_class else "persistent")},
+                       "one class: its own kernel" if one_class else "persistent"),
+                   "plan": "autotuned" if autotune else "default"},
         "roofline": roof,
         "step_ms": {"median": round(step_ms[len(step_ms) // 2], 4), "min": round(step_ms[0], 4),
                     "max": round(step_ms[-1], 4)},
@@ -601,6 +666,26 @@ def main():
         "saturated_pairs": int(stats["n_saturated"]),
         "resident_waves": int(stats["n_waves"]),
     }
+    if autotune is not None:
+        res["autotune"] = autotune
+        # the plain one-launch-per-length-bucket kernels on the same batch and
+        # plan, and a bit-exact comparison of every output of the two styles
+        out_plain = new_out()
+        lp = run_leg(True, out_plain)
+        host_plain = {k: v.cpu().numpy() for k, v in out_plain.items()}
+        ncig = np.minimum(np.abs(host["n_cigar"]), cap)
+        col = np.arange(cap)[None, :] < ncig[:, None]
+        diff = {k: int((host[k] != host_plain[k]).sum()) for k in host if k != "cigar"}
+        diff["cigar"] = int((((host["cigar"] != host_plain["cigar"]) & col).any(axis=1)).sum())
+        res["plain_per_bucket"] = {
+            "value": round(lp["gcups"], 2), "ms_per_step": round(lp["ms"], 4), "kernel_ms": round(lp["fill_ms"], 4),
+            "achieved": round(lp["achieved"], 3), "frac": round(lp["achieved"] / peak, 4),
+            "frac_of_measured": round(lp["achieved"] / peak_meas, 4),
+            "step_ms_median": round(lp["step_ms"][len(lp["step_ms"]) // 2], 4),
+            "outputs_differing_from_persistent": diff, "bit_exact_vs_persistent": all(v == 0 for v in diff.values())}
+        res["persistent_over_plain"] = round(gcups / lp["gcups"], 4)
+        log("c3 persistent %.1f GCUPS, plain %.1f GCUPS, bit-exact %s" % (
+            gcups, lp["gcups"], res["plain_per_bucket"]["bit_exact_vs_persistent"]))
     if args.config == "c1":
         res["small_batch_latency"] = small_batch_latency(ctx)
     if not args.no_serving:

@@ -178,8 +178,9 @@ mica_status_t mica_pack_2bit(const uint8_t *codes, int64_t n_bases, uint32_t *wo
  * and `rows` read rows per lane, lanes * rows >= m_hi; (16, 1..16) or
  * (64, 4), (64, 8), (64, 16).  The default plan is (16, ceil(m/16)) up to 256
  * bases and (64, 16) above.  Lengths not covered keep their plan.  Plans
- * change only speed, never results.  Call between batches: the table is
- * copied to the device synchronously. */
+ * change only speed, never results.  Waits for all work on the device to
+ * finish (batches already enqueued run with the plan they were enqueued
+ * with), then copies the table to the device. */
 mica_status_t mica_ctx_set_plan(mica_ctx_t ctx, int32_t m_lo, int32_t m_hi, int32_t lanes,
                                 int32_t rows);
 
@@ -296,6 +297,15 @@ mica_status_t mica_server_reset_stats(mica_server_t server);
 
 /* Finish the queued work, stop the worker and free everything. */
 mica_status_t mica_server_destroy(mica_server_t server);
+
+/* ---- Measurement -----------------------------------------------------------
+ * Sustained integer VALU throughput of device `hip_device`, the roof the DP
+ * fill kernels are bound by: every lane of 32 resident waves per compute
+ * unit runs eight independent chains of add and max instructions, on packed
+ * 16-bit pairs (*tops_i16x2, a packed instruction counting two operations)
+ * and on 32-bit values (*tops_i32), in tera-operations per second.  Takes a
+ * few milliseconds; synchronises the device. */
+mica_status_t mica_measure_valu_peak(int hip_device, double *tops_i16x2, double *tops_i32);
 
 /* Text of the last non-OK status returned on this host thread. */
 const char *mica_last_error(void);

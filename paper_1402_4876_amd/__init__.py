@@ -24,7 +24,7 @@ from .pack import pack_codes, unpack_words
 from .pipe import Pipeline
 from .serve import Server
 
-__all__ = ["Context", "Server", "align", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
+__all__ = ["Context", "Server", "align", "measure_valu_peak", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
            "PLAIN_LAUNCH", "NO_GRAPH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "MODE_EXTEND", "ST_SATURATED",
            "ST_CIGAR_TRUNC", "ST_LEN_LIMIT", "ST_WIN_OOB", "ST_READ_OOB", "ST_REPETITIVE", "MAX_READ_LEN",
            "MAX_WIN_LEN", "FmIndex", "suffix_array", "Pipeline"]
@@ -120,6 +120,13 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def measure_valu_peak(device=0):
+    """Measured integer VALU throughput (TOP/s): (packed 16-bit, 32-bit)."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _lib.check(_lib.load().mica_measure_valu_peak(int(device), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def pack_2bit(codes, stream=None):

@@ -42,7 +42,7 @@ EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_p
            "mica_server_now", "mica_server_submit", "mica_server_poll", "mica_server_fetch", "mica_server_stats",
            "mica_server_reset_stats", "mica_server_destroy", "mica_last_error", "mica_fm_suffix_array",
            "mica_fm_create", "mica_fm_destroy", "mica_fm_info", "mica_fm_search", "mica_pipe_create",
-           "mica_pipe_run", "mica_pipe_destroy")
+           "mica_pipe_run", "mica_pipe_destroy", "mica_measure_valu_peak")
 
 
 class Scoring(ctypes.Structure):
@@ -126,6 +126,9 @@ def load():
     lib.mica_ctx_destroy.restype = ctypes.c_int
     lib.mica_dp_align_batch.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), u32, P]
     lib.mica_dp_align_batch.restype = ctypes.c_int
+    lib.mica_measure_valu_peak.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
+    lib.mica_measure_valu_peak.restype = ctypes.c_int
     lib.mica_pack_2bit.argtypes = [P, i64, P, P]
     lib.mica_pack_2bit.restype = ctypes.c_int
     lib.mica_ctx_set_plan.argtypes = [P, i32, i32, i32, i32]

@@ -33,11 +33,12 @@ struct TuneBuffers {
   uint64_t* read_off = nullptr;
   int32_t* read_len = nullptr;
   uint8_t* mode = nullptr;
+  int32_t* ext_h0 = nullptr;
   int32_t* out = nullptr;  // 7 arrays of n: score, read_end, ref_end, read_start, ref_start, n_cigar, status
   uint32_t* cigar = nullptr;
   ~TuneBuffers() {
-    for (void* p : {(void*)win_off, (void*)win_len, (void*)read_off, (void*)read_len, (void*)mode, (void*)out,
-                    (void*)cigar})
+    for (void* p : {(void*)win_off, (void*)win_len, (void*)read_off, (void*)read_len, (void*)mode,
+                    (void*)ext_h0, (void*)out, (void*)cigar})
       if (p) (void)hipFree(p);
   }
 };
@@ -74,8 +75,11 @@ mica_status_t gather_up(T* dst, const std::vector<T>& src, const std::vector<int
   return MICA_OK;
 }
 
+// the device copy of the plan table; batches still queued finish first (their
+// fill kernels were chosen from the table they were enqueued with)
 mica_status_t upload_plan(mica_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(c->d_class, c->class_of_m, kMaxM + 1, hipMemcpyHostToDevice));
   return MICA_OK;
 }
@@ -119,12 +123,14 @@ mica_status_t mica_ctx_autotune(mica_ctx_t c, const mica_batch_t* sample, const 
   std::vector<uint64_t> h_woff, h_roff;
   std::vector<int32_t> h_wlen, h_rlen;
   std::vector<uint8_t> h_mode;
+  std::vector<int32_t> h_h0;
   mica_status_t st;
   if ((st = to_host(&h_woff, sample->win_off, n)) != MICA_OK) return st;
   if ((st = to_host(&h_wlen, sample->win_len, n)) != MICA_OK) return st;
   if ((st = to_host(&h_roff, sample->read_off, n)) != MICA_OK) return st;
   if ((st = to_host(&h_rlen, sample->read_len, n)) != MICA_OK) return st;
   if (sample->mode && (st = to_host(&h_mode, sample->mode, n)) != MICA_OK) return st;
+  if (sample->ext_h0 && (st = to_host(&h_h0, sample->ext_h0, n)) != MICA_OK) return st;
 
   // pairs of each read-length range
   const int n_ranges = (sample->max_read_len + kRangeWidth - 1) / kRangeWidth;
@@ -148,6 +154,7 @@ mica_status_t mica_ctx_autotune(mica_ctx_t c, const mica_batch_t* sample, const 
   HIP_TRY(hipMalloc(&tb.read_off, cap_n * sizeof(uint64_t)));
   HIP_TRY(hipMalloc(&tb.read_len, cap_n * sizeof(int32_t)));
   if (sample->mode) HIP_TRY(hipMalloc(&tb.mode, cap_n));
+  if (sample->ext_h0) HIP_TRY(hipMalloc(&tb.ext_h0, cap_n * sizeof(int32_t)));
   HIP_TRY(hipMalloc(&tb.out, 7 * cap_n * sizeof(int32_t)));
   if (cap > 0) HIP_TRY(hipMalloc(&tb.cigar, (size_t)cap_n * cap * sizeof(uint32_t)));
   hipEvent_t e0, e1;
@@ -173,6 +180,8 @@ mica_status_t mica_ctx_autotune(mica_ctx_t c, const mica_batch_t* sample, const 
     if ((st = gather_up(tb.read_off, h_roff, idx)) != MICA_OK) return st;
     if ((st = gather_up(tb.read_len, h_rlen, idx)) != MICA_OK) return st;
     if (sample->mode && (st = gather_up(tb.mode, h_mode, idx)) != MICA_OK) return st;
+    // extension start scores travel with their pairs
+    if (sample->ext_h0 && (st = gather_up(tb.ext_h0, h_h0, idx)) != MICA_OK) return st;
     int max_w = 0;
     for (int64_t p : idx) max_w = std::max(max_w, h_wlen[(size_t)p]);
     mica_batch_t sb = *sample;
@@ -181,6 +190,7 @@ mica_status_t mica_ctx_autotune(mica_ctx_t c, const mica_batch_t* sample, const 
     sb.read_off = tb.read_off;
     sb.read_len = tb.read_len;
     sb.mode = sample->mode ? tb.mode : nullptr;
+    sb.ext_h0 = sample->ext_h0 ? tb.ext_h0 : nullptr;
     sb.n_pairs = sn;
     sb.max_read_len = m_hi;
     sb.max_win_len = max_w;

@@ -28,8 +28,64 @@ constexpr size_t kDefaultWorkspace = size_t(8) << 30;
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Layout of the small device table area of a batch (bucket tables, queue
+// order and counters), in 32-bit words.
+namespace small {
+constexpr size_t kBcount = 0;
+constexpr size_t kBstart = kNumBuckets;
+constexpr size_t kQstart = 2 * kNumBuckets;  // kNumBuckets + 1 entries
+constexpr size_t kQorder = 3 * kNumBuckets + 8;
+constexpr size_t kCounters = 4 * kNumBuckets + 8;
+constexpr size_t kBhead = 4 * kNumBuckets + 8 + kNumCounters;
+constexpr size_t kScount = 5 * kNumBuckets + 8 + kNumCounters;
+constexpr size_t kSfill = kScount + kNumSubBuckets;
+constexpr size_t kWords = kSfill + kNumSubBuckets;
+}  // namespace small
+
+// Work-queue order of the buckets (persistent parts first, each by
+// descending item cost) and the queue positions where each persistent part
+// starts (persist_q[q] .. persist_q[q + 1]).
+void queue_order(uint32_t qorder[kNumBuckets], uint32_t persist_q[kQueueParts]);
+
+// Validation of a batch and its flags shared by the batch entry points:
+// MICA_OK or the batch-level error (with its text recorded).
+mica_status_t check_batch(const mica_batch_t* b, const mica_scoring_t* s, uint32_t flags, uint32_t known_flags);
+
+// The fill launches of a batch, in launch order, and the resident blocks per
+// CU of each (its occupancy at the library's block shape).
+constexpr int kMaxFills = 2 * kNumModes + kNumBuckets + 1;
+struct FillPlan {
+  KernelFn fn[kMaxFills];
+  int occ[kMaxFills];
+  int n = 0;
+  int occ_max = 1;
+  int mode_mask = 0;  // modes the batch holds
+};
+mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch_t* b, const mica_scoring_t* s,
+                         uint32_t flags, FillPlan* out);
+
+// Resident blocks per CU of a fill kernel (cached per device and kernel; no
+// device memory is allocated).
+mica_status_t kernel_occupancy(int device, KernelFn fn, int* blocks);
+
+// Bytes of one resident wave's scratch slot (direction words + CIGAR
+// staging) and its direction-word part; CIGAR staging words per pair.
+struct SlotShape {
+  size_t slot_bytes = 256, dir_bytes = 0;
+  int stage_stride = 0;
+};
+SlotShape slot_shape(const mica_batch_t* b, uint32_t flags);
+
+// LDS bytes of a fill block
+constexpr size_t kFillShmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
+
+// The parameter block of a batch, without its workspace pointers.
+void batch_params(Params* P, const mica_batch_t* b, const mica_scoring_t* s, uint32_t flags, int mode_mask);
+
 // default plan: 16 lanes with the fewest rows that cover m, 64 x 16 above 256
-inline int default_class_of(int m) { return m <= 256 ? (m == 0 ? 0 : (m + 15) / 16 - 1) : 16; }
+__host__ __device__ constexpr int default_class_of(int m) {
+  return m <= 256 ? (m == 0 ? 0 : (m + 15) / 16 - 1) : 16;
+}
 
 }  // namespace mica
 
@@ -38,7 +94,6 @@ struct mica_ctx {
   std::string arch;  // gcnArchName of the device
   size_t ws_cap = mica::kDefaultWorkspace;
   int n_cu = 256;
-  std::map<const void*, int> occ_cache;  // resident blocks per CU of each fill kernel
   // device memory
   mica::Params* d_params = nullptr;     // ring of kParamRing parameter blocks
   uint32_t* d_small = nullptr;    // bucket tables and counters

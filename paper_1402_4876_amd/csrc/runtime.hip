@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -26,16 +27,39 @@ mica_status_t fail(mica_status_t st, const std::string& msg) {
 }  // namespace mica
 
 namespace {
+double bucket_cost(int b);
+}
 
-uint32_t* small_bcount(mica_ctx* c) { return c->d_small; }
-uint32_t* small_bstart(mica_ctx* c) { return c->d_small + kNumBuckets; }
-uint32_t* small_qstart(mica_ctx* c) { return c->d_small + 2 * kNumBuckets; }         // +1 entry
-uint32_t* small_qorder(mica_ctx* c) { return c->d_small + 3 * kNumBuckets + 8; }
-uint32_t* small_counters(mica_ctx* c) { return c->d_small + 4 * kNumBuckets + 8; }
-uint32_t* small_bhead(mica_ctx* c) { return c->d_small + 4 * kNumBuckets + 8 + kNumCounters; }
-uint32_t* small_scount(mica_ctx* c) { return c->d_small + 5 * kNumBuckets + 8 + kNumCounters; }
-uint32_t* small_sfill(mica_ctx* c) { return small_scount(c) + kNumSubBuckets; }
-constexpr size_t kSmallWords = 5 * kNumBuckets + 8 + kNumCounters + 2 * kNumSubBuckets;
+namespace mica {
+
+void queue_order(uint32_t qorder[kNumBuckets], uint32_t persist_q[kQueueParts]) {
+  int order[kNumBuckets];
+  for (int b = 0; b < kNumBuckets; ++b) order[b] = b;
+  // buckets of the persistent kernels first (per mode, long-read part
+  // first), each part by descending item cost, then the plain buckets
+  std::stable_sort(order, order + kNumBuckets, [](int x, int y) {
+    if (queue_part(x) != queue_part(y)) return queue_part(x) < queue_part(y);
+    return bucket_cost(x) > bucket_cost(y);
+  });
+  for (int q = 0; q < kQueueParts; ++q) persist_q[q] = 0;
+  for (int b = 0; b < kNumBuckets; ++b)
+    for (int q = queue_part(b); q + 1 < kQueueParts; ++q) persist_q[q + 1]++;
+  for (int q = 0; q < kNumBuckets; ++q) qorder[q] = (uint32_t)order[q];
+}
+
+}  // namespace mica
+
+namespace {
+
+uint32_t* small_bcount(mica_ctx* c) { return c->d_small + small::kBcount; }
+uint32_t* small_bstart(mica_ctx* c) { return c->d_small + small::kBstart; }
+uint32_t* small_qstart(mica_ctx* c) { return c->d_small + small::kQstart; }
+uint32_t* small_qorder(mica_ctx* c) { return c->d_small + small::kQorder; }
+uint32_t* small_counters(mica_ctx* c) { return c->d_small + small::kCounters; }
+uint32_t* small_bhead(mica_ctx* c) { return c->d_small + small::kBhead; }
+uint32_t* small_scount(mica_ctx* c) { return c->d_small + small::kScount; }
+uint32_t* small_sfill(mica_ctx* c) { return c->d_small + small::kSfill; }
+constexpr size_t kSmallWords = small::kWords;
 
 // cost of one work item of a bucket, for the descending work-queue order
 double bucket_cost(int b) {
@@ -210,6 +234,177 @@ mica_status_t run_sequence(mica_ctx* c, const std::vector<Launch>& seq, const Pa
 
 }  // namespace
 
+namespace mica {
+
+mica_status_t check_batch(const mica_batch_t* b, const mica_scoring_t* s, uint32_t flags, uint32_t known) {
+  if (!b || !s) return fail(MICA_ERR_INVALID_ARG, "NULL batch or scoring");
+  if (flags & ~known) return fail(MICA_ERR_INVALID_ARG, "unknown flag bits");
+  if (s->match < 1 || s->match > 4096 || s->mismatch > 0 || s->mismatch < -4096 || s->gap_open < 0 ||
+      s->gap_open > 4096 || s->gap_extend < 1 || s->gap_extend > 4096)
+    return fail(MICA_ERR_INVALID_ARG, "scoring outside its limits");
+  if (b->n_pairs < 0) return fail(MICA_ERR_INVALID_ARG, "n_pairs < 0");
+  if (b->n_pairs > 0xFFFFFFF0ll) return fail(MICA_ERR_LIMIT, "too many pairs in one batch");
+  if (b->default_mode < 0 || b->default_mode > 2) return fail(MICA_ERR_INVALID_ARG, "bad default_mode");
+  if (b->mode_mask < 0 || b->mode_mask > 7) return fail(MICA_ERR_INVALID_ARG, "bad mode_mask");
+  if (b->ext_clip < 0 || b->ext_clip > kMaxH0 || b->ext_default_h0 < 0 || b->ext_default_h0 > kMaxH0)
+    return fail(MICA_ERR_INVALID_ARG, "extension start score or clipping penalty outside 0..2^20");
+  if (b->max_read_len < 0 || b->max_read_len > kMaxM || b->max_win_len < 0 || b->max_win_len > kMaxN)
+    return fail(MICA_ERR_LIMIT, "max_read_len / max_win_len beyond the library limits");
+  if (b->min_read_len < 0 || b->min_read_len > b->max_read_len)
+    return fail(MICA_ERR_INVALID_ARG, "min_read_len outside [0, max_read_len]");
+  const bool want_cigar = flags & MICA_OUT_CIGAR;
+  const bool want_start = want_cigar || (flags & MICA_OUT_START);
+  if (b->n_pairs == 0) return MICA_OK;
+  if (!b->ref2b || !b->win_off || !b->win_len || !b->reads2b || !b->read_off || !b->read_len ||
+      !b->score || !b->read_end || !b->ref_end || !b->status)
+    return fail(MICA_ERR_INVALID_ARG, "NULL input or output pointer");
+  if (want_start && (!b->read_start || !b->ref_start))
+    return fail(MICA_ERR_INVALID_ARG, "read_start / ref_start required for start or CIGAR output");
+  if (want_cigar && (!b->n_cigar || b->cigar_cap < 0 || (b->cigar_cap > 0 && !b->cigar)))
+    return fail(MICA_ERR_INVALID_ARG, "cigar / n_cigar / cigar_cap invalid");
+  return MICA_OK;
+}
+
+namespace {
+struct OccEntry {
+  int device;
+  KernelFn fn;
+  int blocks;
+};
+constexpr int kOccCache = 1024;
+OccEntry g_occ[kOccCache];
+int g_n_occ = 0;
+std::mutex g_occ_mu;
+}  // namespace
+
+mica_status_t kernel_occupancy(int device, KernelFn fn, int* blocks) {
+  std::lock_guard<std::mutex> g(g_occ_mu);
+  for (int i = 0; i < g_n_occ; ++i)
+    if (g_occ[i].device == device && g_occ[i].fn == fn) {
+      *blocks = g_occ[i].blocks;
+      return MICA_OK;
+    }
+  int nb = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, 256, kFillShmem));
+  nb = std::max(nb, 1);
+  if (g_n_occ < kOccCache) g_occ[g_n_occ++] = {device, fn, nb};
+  *blocks = nb;
+  return MICA_OK;
+}
+
+mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch_t* b, const mica_scoring_t* s,
+                         uint32_t flags, FillPlan* out) {
+  const KernelTable& K = kernels();
+  FillPlan& fp = *out;
+  fp.n = 0;
+  fp.occ_max = 1;
+  const int max_m = b->max_read_len, max_n = b->max_win_len;
+  const int d = (flags & (MICA_OUT_CIGAR | MICA_OUT_START)) ? 1 : 0;
+  const bool forced = flags & MICA_FORCE_INT32;
+  const int mode_mask = b->mode ? (b->mode_mask ? b->mode_mask : 7) : 1 << b->default_mode;
+  fp.mode_mask = mode_mask;
+  const bool any_sg = mode_mask & 1, any_local = mode_mask & 2, any_ext = mode_mask & 4;
+  const bool any_mode[3] = {any_sg, any_local, any_ext};
+  // extensions start from per-pair scores the host does not read: their
+  // saturating variants are always available
+  const bool may_sat = !forced && (any_ext || !int16_always_safe(max_m, max_n, *s, any_local, any_sg));
+  const bool plain = flags & MICA_PLAIN_LAUNCH;
+  bool cls_used[kNumClasses] = {};
+  for (int m = std::max(1, b->min_read_len); m <= max_m; ++m) cls_used[class_of_m[m]] = true;
+  // a batch of one persistent class gains nothing from the persistent
+  // kernels (they balance classes against each other) and its plain kernel
+  // is compiled for that class alone
+  int n_persist_cls = 0;
+  for (int cls = 0; cls <= kPersistMaxClass; ++cls)
+    if (cls_used[cls] && class_lanes(cls) == 16) ++n_persist_cls;
+  const bool persist = !plain && !forced && n_persist_cls > 1;
+  if (persist) {
+    // persistent parts in queue order: per mode, long reads first
+    bool part_used[2] = {false, false};
+    for (int cls = 0; cls <= kPersistMaxClass; ++cls)
+      if (cls_used[cls] && class_lanes(cls) == 16) part_used[persist_part(cls)] = true;
+    for (int md = 0; md < kNumModes; ++md) {
+      if (!any_mode[md]) continue;
+      for (int part : {1, 0})
+        if (part_used[part]) fp.fn[fp.n++] = K.persistent[d][md][part];
+    }
+  }
+  // plain launches: every bucket in plain mode, else the buckets the
+  // persistent kernels do not serve
+  for (int kind = 0; kind < kNumKinds; ++kind) {
+    if (forced != (kind == kK32)) continue;
+    if (kind == kK16Sat && !may_sat) continue;
+    for (int cls = 0; cls < kNumClasses; ++cls) {
+      if (!cls_used[cls]) continue;
+      for (int md = 0; md < kNumModes; ++md) {
+        if (!any_mode[md]) continue;
+        const int bk = bucket_id(kind, cls, md);
+        if (persist && persistent_bucket(bk)) continue;
+        fp.fn[fp.n++] = K.bucket[d][bk];
+      }
+    }
+  }
+  if (may_sat) fp.fn[fp.n++] = K.rerun[d];
+  for (int i = 0; i < fp.n; ++i) {
+    mica_status_t st = kernel_occupancy(device, fp.fn[i], &fp.occ[i]);
+    if (st != MICA_OK) return st;
+    fp.occ_max = std::max(fp.occ_max, fp.occ[i]);
+  }
+  return MICA_OK;
+}
+
+SlotShape slot_shape(const mica_batch_t* b, uint32_t flags) {
+  SlotShape sh;
+  const int d = (flags & (MICA_OUT_CIGAR | MICA_OUT_START)) ? 1 : 0;
+  sh.dir_bytes = d ? (size_t)(b->max_win_len + 64) * 64 * 16 : 0;
+  sh.stage_stride = b->max_read_len + b->max_win_len + 2;
+  const size_t stage_bytes = d ? (size_t)8 * sh.stage_stride * 4 : 0;
+  sh.slot_bytes = std::max<size_t>(align_up(sh.dir_bytes + stage_bytes, 256), 256);
+  return sh;
+}
+
+void batch_params(Params* P_, const mica_batch_t* b, const mica_scoring_t* s, uint32_t flags, int mode_mask) {
+  Params& P = *P_;
+  const bool want_cigar = flags & MICA_OUT_CIGAR;
+  const bool want_start = want_cigar || (flags & MICA_OUT_START);
+  std::memset(&P, 0, sizeof(P));
+  P.ref2b = b->ref2b;
+  P.ref_len = b->ref_len;
+  P.win_off = b->win_off;
+  P.win_len = b->win_len;
+  P.reads2b = b->reads2b;
+  P.reads_len = b->reads_len;
+  P.read_off = b->read_off;
+  P.read_len = b->read_len;
+  P.mode = b->mode;
+  P.default_mode = b->default_mode;
+  P.ext_h0 = b->ext_h0;
+  P.ext_default_h0 = b->ext_default_h0;
+  P.ext_clip = b->ext_clip;
+  P.mode_mask = mode_mask;
+  P.max_m = b->max_read_len;
+  P.min_m = b->min_read_len;
+  P.max_n = b->max_win_len;
+  P.n_pairs = b->n_pairs;
+  P.score = b->score;
+  P.read_end = b->read_end;
+  P.ref_end = b->ref_end;
+  P.read_start = want_start ? b->read_start : nullptr;
+  P.ref_start = want_start ? b->ref_start : nullptr;
+  P.cigar = want_cigar ? b->cigar : nullptr;
+  P.cigar_cap = want_cigar ? b->cigar_cap : 0;
+  P.n_cigar = want_cigar ? b->n_cigar : nullptr;
+  P.status = b->status;
+  P.sa = s->match;
+  P.sb = s->mismatch;
+  P.so = s->gap_open;
+  P.se = s->gap_extend;
+  P.flags = (want_start ? kOutStart : 0u) | (want_cigar ? kOutCigar : 0u) |
+            ((flags & MICA_FORCE_INT32) ? kForceInt32 : 0u);
+}
+
+}  // namespace mica
+
 extern "C" {
 
 const char* mica_last_error(void) { return g_last_error.c_str(); }
@@ -238,18 +433,7 @@ mica_status_t mica_ctx_create(int hip_device, size_t workspace_bytes, mica_ctx_t
   HIP_TRY(hipHostMalloc((void**)&c->h_params, sizeof(Params) * kParamRing, hipHostMallocDefault));
   for (int i = 0; i < kParamRing; ++i) HIP_TRY(hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming));
   default_plan(c);
-  // queue order: buckets by descending item cost
-  int order[kNumBuckets];
-  for (int b = 0; b < kNumBuckets; ++b) order[b] = b;
-  // buckets of the persistent kernels first (semi-global, then local), each
-  // part by descending item cost
-  std::stable_sort(order, order + kNumBuckets, [](int x, int y) {
-    if (queue_part(x) != queue_part(y)) return queue_part(x) < queue_part(y);
-    return bucket_cost(x) > bucket_cost(y);
-  });
-  for (int b = 0; b < kNumBuckets; ++b)
-    for (int q = queue_part(b); q + 1 < kQueueParts; ++q) c->persist_q[q + 1]++;
-  for (int q = 0; q < kNumBuckets; ++q) c->qorder[q] = (uint32_t)order[q];
+  queue_order(c->qorder, c->persist_q);
   HIP_TRY(hipMemcpy(small_qorder(c), c->qorder, sizeof(c->qorder), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_class, c->class_of_m, kMaxM + 1, hipMemcpyHostToDevice));
   c->class_dirty = false;
@@ -288,8 +472,12 @@ mica_status_t mica_ctx_set_plan(mica_ctx_t c, int32_t m_lo, int32_t m_hi, int32_
   const int cls = class_of(lanes, rows);
   if (cls < 0) return fail(MICA_ERR_INVALID_ARG, "unsupported (lanes, rows)");
   if (lanes * rows < m_hi) return fail(MICA_ERR_INVALID_ARG, "lanes * rows must cover m_hi");
-  for (int m = m_lo; m <= m_hi; ++m) c->class_of_m[m] = (uint8_t)cls;
   HIP_TRY(hipSetDevice(c->device));
+  // a batch still queued on any stream reads the device table when its
+  // planning kernel runs, but its fill kernels were chosen from the host
+  // table when it was enqueued: let every such batch finish first
+  HIP_TRY(hipDeviceSynchronize());
+  for (int m = m_lo; m <= m_hi; ++m) c->class_of_m[m] = (uint8_t)cls;
   HIP_TRY(hipMemcpy(c->d_class, c->class_of_m, kMaxM + 1, hipMemcpyHostToDevice));
   return MICA_OK;
 }
@@ -303,118 +491,36 @@ mica_status_t mica_pack_2bit(const uint8_t* codes, int64_t n_bases, uint32_t* wo
 
 mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mica_scoring_t* s,
                                   uint32_t flags, void* stream_) {
-  if (!c || !b || !s) return fail(MICA_ERR_INVALID_ARG, "NULL ctx, batch or scoring");
+  if (!c) return fail(MICA_ERR_INVALID_ARG, "NULL ctx");
   const uint32_t known = MICA_OUT_START | MICA_OUT_CIGAR | MICA_FORCE_INT32 | MICA_PLAIN_LAUNCH | MICA_NO_GRAPH;
-  if (flags & ~known) return fail(MICA_ERR_INVALID_ARG, "unknown flag bits");
-  if (s->match < 1 || s->match > 4096 || s->mismatch > 0 || s->mismatch < -4096 || s->gap_open < 0 ||
-      s->gap_open > 4096 || s->gap_extend < 1 || s->gap_extend > 4096)
-    return fail(MICA_ERR_INVALID_ARG, "scoring outside its limits");
-  if (b->n_pairs < 0) return fail(MICA_ERR_INVALID_ARG, "n_pairs < 0");
-  if (b->n_pairs > 0xFFFFFFF0ll) return fail(MICA_ERR_LIMIT, "too many pairs in one batch");
-  if (b->default_mode < 0 || b->default_mode > 2) return fail(MICA_ERR_INVALID_ARG, "bad default_mode");
-  if (b->mode_mask < 0 || b->mode_mask > 7) return fail(MICA_ERR_INVALID_ARG, "bad mode_mask");
-  if (b->ext_clip < 0 || b->ext_clip > kMaxH0 || b->ext_default_h0 < 0 || b->ext_default_h0 > kMaxH0)
-    return fail(MICA_ERR_INVALID_ARG, "extension start score or clipping penalty outside 0..2^20");
-  if (b->max_read_len < 0 || b->max_read_len > kMaxM || b->max_win_len < 0 || b->max_win_len > kMaxN)
-    return fail(MICA_ERR_LIMIT, "max_read_len / max_win_len beyond the library limits");
-  if (b->min_read_len < 0 || b->min_read_len > b->max_read_len)
-    return fail(MICA_ERR_INVALID_ARG, "min_read_len outside [0, max_read_len]");
-  const bool want_cigar = flags & MICA_OUT_CIGAR;
-  const bool want_start = want_cigar || (flags & MICA_OUT_START);
+  mica_status_t st = check_batch(b, s, flags, known);
+  if (st != MICA_OK) return st;
   if (b->n_pairs == 0) return MICA_OK;
-  if (!b->ref2b || !b->win_off || !b->win_len || !b->reads2b || !b->read_off || !b->read_len ||
-      !b->score || !b->read_end || !b->ref_end || !b->status)
-    return fail(MICA_ERR_INVALID_ARG, "NULL input or output pointer");
-  if (want_start && (!b->read_start || !b->ref_start))
-    return fail(MICA_ERR_INVALID_ARG, "read_start / ref_start required for start or CIGAR output");
-  if (want_cigar && (!b->n_cigar || b->cigar_cap < 0 || (b->cigar_cap > 0 && !b->cigar)))
-    return fail(MICA_ERR_INVALID_ARG, "cigar / n_cigar / cigar_cap invalid");
   hipStream_t stream = (hipStream_t)stream_;
   HIP_TRY(hipSetDevice(c->device));
 
-  mica_status_t st = ensure_pairs(c, b->n_pairs);
+  st = ensure_pairs(c, b->n_pairs);
   if (st != MICA_OK) return st;
 
   // fill launches of this batch
-  const KernelTable& K = kernels();
-  const int max_m = b->max_read_len, max_n = b->max_win_len;
-  const int d = (want_cigar || (flags & MICA_OUT_START)) ? 1 : 0;
-  const bool forced = flags & MICA_FORCE_INT32;
-  const int mode_mask = b->mode ? (b->mode_mask ? b->mode_mask : 7) : 1 << b->default_mode;
-  const bool any_sg = mode_mask & 1, any_local = mode_mask & 2, any_ext = mode_mask & 4;
-  const bool any_mode[3] = {any_sg, any_local, any_ext};
-  // extensions start from per-pair scores the host does not read: their
-  // saturating variants are always available
-  const bool may_sat = !forced && (any_ext || !int16_always_safe(max_m, max_n, *s, any_local, any_sg));
-  const bool plain = flags & MICA_PLAIN_LAUNCH;
-  bool cls_used[kNumClasses] = {};
-  for (int m = std::max(1, b->min_read_len); m <= max_m; ++m) cls_used[c->class_of_m[m]] = true;
-  // a batch of one persistent class gains nothing from the persistent
-  // kernels (they balance classes against each other) and its plain kernel
-  // is compiled for that class alone
-  int n_persist_cls = 0;
-  for (int cls = 0; cls <= kPersistMaxClass; ++cls)
-    if (cls_used[cls] && class_lanes(cls) == 16) ++n_persist_cls;
-  const bool persist = !plain && !forced && n_persist_cls > 1;
-  std::vector<KernelFn> fills;
-  if (persist) {
-    // persistent parts in queue order: per mode, long reads first
-    bool part_used[2] = {false, false};
-    for (int cls = 0; cls <= kPersistMaxClass; ++cls)
-      if (cls_used[cls] && class_lanes(cls) == 16) part_used[persist_part(cls)] = true;
-    for (int md = 0; md < kNumModes; ++md) {
-      if (!any_mode[md]) continue;
-      for (int part : {1, 0})
-        if (part_used[part]) fills.push_back(K.persistent[d][md][part]);
-    }
-  }
-  // plain launches: every bucket in plain mode, else the buckets the
-  // persistent kernels do not serve
-  for (int kind = 0; kind < kNumKinds; ++kind) {
-    if (forced != (kind == kK32)) continue;
-    if (kind == kK16Sat && !may_sat) continue;
-    for (int cls = 0; cls < kNumClasses; ++cls) {
-      if (!cls_used[cls]) continue;
-      for (int md = 0; md < kNumModes; ++md) {
-        if (!any_mode[md]) continue;
-        const int bk = bucket_id(kind, cls, md);
-        if (persist && persistent_bucket(bk)) continue;
-        fills.push_back(K.bucket[d][bk]);
-      }
-    }
-  }
-  if (may_sat) fills.push_back(K.rerun[d]);
+  FillPlan fp;
+  st = plan_fills(c->device, c->class_of_m, b, s, flags, &fp);
+  if (st != MICA_OK) return st;
 
   // scratch: direction bits of a resident wave (steps x 64 lanes x 16 B) +
   // CIGAR staging, for as many waves as the most occupant fill kernel keeps
   // resident
-  const size_t shmem = (size_t)kWavesPerBlock * kLdsWaveWords * 4;
-  std::vector<int> occ(fills.size());
-  int occ_max = 1;
-  for (size_t i = 0; i < fills.size(); ++i) {
-    auto it = c->occ_cache.find((const void*)fills[i]);
-    if (it == c->occ_cache.end()) {
-      int nb = 0;
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fills[i], 256, shmem));
-      it = c->occ_cache.emplace((const void*)fills[i], std::max(nb, 1)).first;
-    }
-    occ[i] = it->second;
-    occ_max = std::max(occ_max, occ[i]);
-  }
-  const size_t dir_bytes = d ? (size_t)(max_n + 64) * 64 * 16 : 0;
-  const int stage_stride = max_m + max_n + 2;
-  const size_t stage_bytes = d ? (size_t)8 * stage_stride * 4 : 0;
-  const size_t slot_bytes = std::max<size_t>(align_up(dir_bytes + stage_bytes, 256), 256);
-  int64_t slots = (int64_t)occ_max * c->n_cu * kWavesPerBlock;
-  const int64_t by_ws = (int64_t)(c->ws_cap / slot_bytes);
+  const SlotShape sh = slot_shape(b, flags);
+  int64_t slots = (int64_t)fp.occ_max * c->n_cu * kWavesPerBlock;
+  const int64_t by_ws = (int64_t)(c->ws_cap / sh.slot_bytes);
   slots = std::min(slots, by_ws);
   const int64_t need = (b->n_pairs + 1) / 2 + 3;  // upper bound of work items
   slots = std::min(slots, need);
   slots = std::max<int64_t>(align_up((size_t)std::max<int64_t>(slots, 1), kWavesPerBlock), kWavesPerBlock);
-  if ((size_t)slots * slot_bytes > c->ws_cap && slots > kWavesPerBlock)
-    slots = (int64_t)(c->ws_cap / slot_bytes) / kWavesPerBlock * kWavesPerBlock;
+  if ((size_t)slots * sh.slot_bytes > c->ws_cap && slots > kWavesPerBlock)
+    slots = (int64_t)(c->ws_cap / sh.slot_bytes) / kWavesPerBlock * kWavesPerBlock;
   if (slots < kWavesPerBlock) return fail(MICA_ERR_OUT_OF_MEMORY, "workspace too small for one block");
-  st = ensure_scratch(c, (size_t)slots * slot_bytes);
+  st = ensure_scratch(c, (size_t)slots * sh.slot_bytes);
   if (st != MICA_OK) return st;
 
   // parameter block (pinned ring slot, copied on the stream)
@@ -422,40 +528,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   c->ring_pos = (c->ring_pos + 1) % kParamRing;
   if (c->ev_used[rp]) HIP_TRY(hipEventSynchronize(c->ev[rp]));
   Params& P = c->h_params[rp];
-  std::memset(&P, 0, sizeof(P));
-  P.ref2b = b->ref2b;
-  P.ref_len = b->ref_len;
-  P.win_off = b->win_off;
-  P.win_len = b->win_len;
-  P.reads2b = b->reads2b;
-  P.reads_len = b->reads_len;
-  P.read_off = b->read_off;
-  P.read_len = b->read_len;
-  P.mode = b->mode;
-  P.default_mode = b->default_mode;
-  P.ext_h0 = b->ext_h0;
-  P.ext_default_h0 = b->ext_default_h0;
-  P.ext_clip = b->ext_clip;
-  P.mode_mask = mode_mask;
-  P.max_m = max_m;
-  P.min_m = b->min_read_len;
-  P.max_n = max_n;
-  P.n_pairs = b->n_pairs;
-  P.score = b->score;
-  P.read_end = b->read_end;
-  P.ref_end = b->ref_end;
-  P.read_start = want_start ? b->read_start : nullptr;
-  P.ref_start = want_start ? b->ref_start : nullptr;
-  P.cigar = want_cigar ? b->cigar : nullptr;
-  P.cigar_cap = want_cigar ? b->cigar_cap : 0;
-  P.n_cigar = want_cigar ? b->n_cigar : nullptr;
-  P.status = b->status;
-  P.sa = s->match;
-  P.sb = s->mismatch;
-  P.so = s->gap_open;
-  P.se = s->gap_extend;
-  P.flags = (want_start ? kOutStart : 0u) | (want_cigar ? kOutCigar : 0u) |
-            ((flags & MICA_FORCE_INT32) ? kForceInt32 : 0u);
+  batch_params(&P, b, s, flags, fp.mode_mask);
   P.bucket_of = c->d_pairs;
   P.sorted = c->d_pairs + c->pair_cap;
   P.rerun = c->d_pairs + 2 * c->pair_cap;
@@ -469,9 +542,9 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.counters = small_counters(c);
   P.bhead = small_bhead(c);
   P.scratch = c->d_scratch;
-  P.slot_bytes = slot_bytes;
-  P.dir_bytes = dir_bytes;
-  P.stage_stride = stage_stride;
+  P.slot_bytes = sh.slot_bytes;
+  P.dir_bytes = sh.dir_bytes;
+  P.stage_stride = sh.stage_stride;
   P.n_slots = (int32_t)slots;
   for (int i = 0; i < kQueueParts; ++i) P.persist_q[i] = c->persist_q[i];
   Params* dp = c->d_params + rp;
@@ -479,17 +552,18 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   HIP_TRY(hipEventRecord(c->ev[rp], stream));
   c->ev_used[rp] = true;
 
+  const KernelTable& K = kernels();
   const unsigned pblocks = (unsigned)((b->n_pairs + kPlanPairsPerBlock - 1) / kPlanPairsPerBlock);
   std::vector<Launch> seq;
   seq.push_back({K.zero, 1, 256, 0, false});
   seq.push_back({K.plan, pblocks, kPlanThreads, 0, false});
   seq.push_back({K.scan, 1, 256, 0, false});
   seq.push_back({K.scatter, pblocks, kPlanThreads, 0, false});
-  for (size_t i = 0; i < fills.size(); ++i) {
+  for (int i = 0; i < fp.n; ++i) {
     // each fill kernel gets the blocks it keeps resident (its waves index
     // the first slots of the scratch)
-    const int64_t blocks = std::min<int64_t>((int64_t)occ[i] * c->n_cu, slots / kWavesPerBlock);
-    seq.push_back({fills[i], (unsigned)std::max<int64_t>(blocks, 1), 256, shmem, true});
+    const int64_t blocks = std::min<int64_t>((int64_t)fp.occ[i] * c->n_cu, slots / kWavesPerBlock);
+    seq.push_back({fp.fn[i], (unsigned)std::max<int64_t>(blocks, 1), 256, kFillShmem, true});
   }
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (c->timing) {
@@ -501,7 +575,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   if (c->timing) c->ev_pending.emplace_back(t0, t1);
   c->last_pairs = b->n_pairs;
   c->last_slots = (int)slots;
-  c->last_scratch = (size_t)slots * slot_bytes;
+  c->last_scratch = (size_t)slots * sh.slot_bytes;
   return MICA_OK;
 }
 

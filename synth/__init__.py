@@ -405,3 +405,81 @@ def serving_like(n_pairs, ref_len=4_000_000, seed=0):
     codes, s, e, _ = _draw_reads(rng, lambda pos: ref[pos], win_off, win_off + nn - mm - 8, mm,
                                  lambda idx: win_off[idx] + nn[idx], 0.01, 0.003, "geom", False)
     return _finish("c4like", ref, win_off, nn, codes, mm, np.zeros(n_pairs), s - win_off, e - win_off)
+
+
+def pack_reads_unaligned(rng, codes, m):
+    """Concatenate reads with 0..15 random filler bases before each one, so
+    read offsets take every residue mod 16 (a word boundary anywhere in a
+    read).  Returns (flat codes, offsets)."""
+    N = len(m)
+    gap = rng.integers(0, 16, N).astype(np.int64)
+    off = np.zeros(N, np.int64)
+    pos = 0
+    for k in range(N):
+        pos += int(gap[k])
+        off[k] = pos
+        pos += int(m[k])
+    flat = rng.integers(0, 4, max(pos, 1) + 16, dtype=np.uint8)
+    for k in range(N):
+        flat[off[k]:off[k] + m[k]] = codes[k, :m[k]]
+    return flat, off
+
+
+LONG_REF_LEN = (1 << 32) + (1 << 26)  # 4.36 Gbp: window offsets past 2^31 and 2^32
+
+
+def long_reference_batch(n_pairs=4000, ref_len=LONG_REF_LEN, hot_len=1 << 16, seed=0, modes=(0, 1, 2)):
+    """Pairs whose windows sit past base 2^31 and 2^32 of a reference longer
+    than 2^32 bases, for parity at the offsets a 3 Gbp resident reference
+    reaches.
+
+    The packed reference is zero words (all A) except for stretches of
+    hot_len i.i.d. bases that start just below 2^31, straddle 2^31, straddle
+    2^32, end at the last base, and start at 0; every window lies inside one
+    stretch.  Reads of U{1..260} bases (windows 1.5 m + 64) are planted with
+    config-1 errors; modes cycle over `modes` (extension pairs get h0 U{19..60});
+    reads sit at unaligned offsets (pack_reads_unaligned).
+    Returns (batch with ref = packed words and absolute win_off, stretch starts)."""
+    assert ref_len % 16 == 0 and ref_len > (1 << 32) + 2 * hot_len
+    rng = rng_for(12, seed)
+    words = np.zeros(ref_len // 16, np.uint32)
+    starts = np.array([(1 << 31) - hot_len, (1 << 31) - hot_len // 2, (1 << 32) - hot_len // 2,
+                       ref_len - hot_len, 0], np.int64)
+    for s in starts:
+        words[s // 16:(s + hot_len) // 16] = random_packed_ref(rng, hot_len)
+    m = rng.integers(1, 261, n_pairs).astype(np.int32)
+    n = (3 * m) // 2 + 64
+    region = starts[rng.integers(0, len(starts), n_pairs)]
+    win_off = region + rng.integers(0, hot_len - n + 1).astype(np.int64)
+    # every tenth window straddles 2^31, the next 2^32; the next ends at the last base
+    k = np.arange(n_pairs)
+    for r, edge in ((0, 1 << 31), (1, 1 << 32)):
+        sel = k % 10 == r
+        win_off[sel] = edge - rng.integers(1, n[sel]).astype(np.int64)
+    win_off[k % 10 == 2] = ref_len - n[k % 10 == 2].astype(np.int64)
+    codes, s, e, _ = _draw_reads(rng, lambda pos: base_at_packed(words, pos), win_off, win_off + n - m - 8, m,
+                                 lambda idx: win_off[idx] + n[idx], 0.01, 0.003, "geom", False)
+    # a fifth of the reads are random (low scores, long local tracebacks)
+    junk = rng.random(n_pairs) < 0.2
+    codes[junk] = rng.integers(0, 4, (int(junk.sum()), codes.shape[1]), dtype=np.uint8)
+    reads, read_off = pack_reads_unaligned(rng, codes, m)
+    mode = np.asarray(modes, np.uint8)[np.arange(n_pairs) % len(modes)]
+    b = Batch(ref=words, win_off=win_off, win_len=n.astype(np.int32), reads=reads, read_off=read_off,
+              read_len=m, mode=mode, name="longref", ref_packed=True)
+    b.h0 = np.where(mode == 2, rng.integers(19, 61, n_pairs), 0).astype(np.int32)
+    return b, starts
+
+
+def rebase_windows(batch):
+    """The same pairs with every window copied out of the (packed) reference
+    into a small code array (windows back to back, offsets rebased); reads,
+    modes and h0 unchanged.  The oracle aligns this copy."""
+    n = batch.win_len.astype(np.int64)
+    off = np.zeros(batch.n_pairs, np.int64)
+    if batch.n_pairs:
+        off[1:] = np.cumsum(n)[:-1]
+    pos = np.concatenate([batch.win_off[p] + np.arange(n[p], dtype=np.int64) for p in range(batch.n_pairs)]
+                         + [np.zeros(0, np.int64)])
+    ref = base_at_packed(batch.ref, pos) if batch.ref_packed else batch.ref[pos]
+    ref = np.concatenate([ref, np.zeros(16, np.uint8)])
+    return dataclasses.replace(batch, ref=ref, win_off=off, ref_packed=False)

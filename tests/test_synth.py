@@ -90,3 +90,25 @@ def test_determinism_and_config_shapes():
     assert 0.08 < c2.random_partner.mean() < 0.12
     s = synth.serving_like(500)
     assert set(np.unique(s.read_len)) <= {100, 150, 250}
+
+
+def test_long_reference_batch_offsets_and_rebase():
+    """Windows past 2^31 and 2^32 of a > 4 Gbp packed reference, each inside a
+    random stretch; unaligned read offsets; the rebased copy holds the same
+    window bases and reads."""
+    b, starts = synth.long_reference_batch(600)
+    assert len(b.ref) * 16 == synth.LONG_REF_LEN > (1 << 32)
+    end = b.win_off + b.win_len
+    assert ((b.win_off < (1 << 31)) & (end > (1 << 31))).sum() >= 50
+    assert ((b.win_off < (1 << 32)) & (end > (1 << 32))).sum() >= 50
+    assert (end == synth.LONG_REF_LEN).sum() >= 50 and (end <= synth.LONG_REF_LEN).all()
+    inside = np.zeros(b.n_pairs, bool)
+    for s0 in starts:
+        inside |= (b.win_off >= s0) & (end <= s0 + (1 << 16))
+    assert inside.all()
+    assert len(np.unique(b.read_off % 16)) == 16
+    small = synth.rebase_windows(b)
+    assert small.ref_packed is False and len(small.ref) == int(b.win_len.sum()) + 16
+    for p in range(0, b.n_pairs, 7):
+        assert np.array_equal(small.window_codes(p), b.window_codes(p))
+        assert np.array_equal(small.read_codes(p), b.read_codes(p))
