@@ -169,6 +169,33 @@ typedef struct {
 mica_status_t mica_dp_align_batch(mica_ctx_t ctx, const mica_batch_t *batch,
                                   const mica_scoring_t *scoring, uint32_t flags, void *stream);
 
+/* ---- Allocation-free batch call -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Same alignment, outputs and errors as mica_dp_align_batch (default plan,
+ * kernels launched one by one, never a HIP graph), without a context: every
+ * piece of device workspace (parameter block, bucket tables and counters,
+ * per-pair work lists, traceback slots) lives in one fixed device array of
+ * MICA_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds from
+ * the first such call until the process ends.  The call itself allocates
+ * and frees no device memory.  Runs on the calling thread's current HIP
+ * device; the first call on a device looks up the array's address there.
+ * Limits: at most MICA_NOALLOC_MAX_PAIRS pairs (MICA_ERR_LIMIT above), and
+ * the traceback slots of one block of four waves must fit the array
+ * (always true within MICA_MAX_READ_LEN / MICA_MAX_WIN_LEN); fewer waves
+ * than the GPU could keep resident may run when windows are long.
+ * The array is shared by every call on that GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (on any streams, from any
+ * threads) race and give wrong results; order them on one stream or
+ * synchronise between them.  Flags: MICA_OUT_START, MICA_OUT_CIGAR,
+ * MICA_FORCE_INT32, MICA_PLAIN_LAUNCH (MICA_NO_GRAPH is accepted and has
+ * no effect). */
+#define MICA_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+#define MICA_NOALLOC_MAX_PAIRS ((int64_t)1 << 22)
+mica_status_t mica_dp_align_batch_noalloc(const mica_batch_t *batch, const mica_scoring_t *scoring,
+                                          uint32_t flags, void *stream);
+
 /* Pack n_bases base codes (one byte each, values 0..3) from device memory
  * `codes` into 2-bit words at device pointer `words` (ceil(n/16) words; the
  * unused high bits of the last word are zero).  Async on `stream`. */

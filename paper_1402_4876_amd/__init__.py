@@ -24,7 +24,7 @@ from .pack import pack_codes, unpack_words
 from .pipe import Pipeline
 from .serve import Server
 
-__all__ = ["Context", "Server", "align", "measure_valu_peak", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
+__all__ = ["Context", "Server", "align", "align_noalloc", "measure_valu_peak", "pack_2bit", "pack_codes", "unpack_words", "MicaError", "FORCE_INT32",
            "PLAIN_LAUNCH", "NO_GRAPH", "OUT_START", "OUT_CIGAR", "MODE_LOCAL", "MODE_SEMIGLOBAL", "MODE_EXTEND", "ST_SATURATED",
            "ST_CIGAR_TRUNC", "ST_LEN_LIMIT", "ST_WIN_OOB", "ST_READ_OOB", "ST_REPETITIVE", "MAX_READ_LEN",
            "MAX_WIN_LEN", "FmIndex", "suffix_array", "Pipeline"]
@@ -211,6 +211,25 @@ def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scor
     flags = (OUT_START if out_start else 0) | (OUT_CIGAR if out_cigar else 0) | \
         (FORCE_INT32 if force_int32 else 0) | (PLAIN_LAUNCH if plain else 0) | (0 if graph else NO_GRAPH)
     return b, sc, flags, out
+
+
+def align_noalloc(ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, scoring=(1, -4, 6, 1),
+                  out_start=False, out_cigar=False, cigar_cap=64, force_int32=False, plain=False,
+                  default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
+                  reads_len=None, out=None, stream=None, ext_h0=None, ext_default_h0=0, ext_clip=0,
+                  mode_mask=0, min_read_len=0):
+    """The allocation-free call (mica_dp_align_batch_noalloc): same arguments
+    and results as align() without a context; the library's workspace is one
+    fixed device array per GPU, so overlapping calls on one GPU race.  Pass
+    ``out`` (preallocated tensors) when the caller must not allocate either."""
+    b, sc, flags, out = _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring,
+                                    out_start, out_cigar, cigar_cap, force_int32, plain, False, default_mode,
+                                    max_read_len, max_win_len, ref_len, reads_len, out, ext_h0=ext_h0,
+                                    ext_default_h0=ext_default_h0, ext_clip=ext_clip, mode_mask=mode_mask,
+                                    min_read_len=min_read_len)
+    _lib.check(_lib.load().mica_dp_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc), flags,
+                                                       _stream_handle(stream)))
+    return out
 
 
 def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, scoring=(1, -4, 6, 1),

@@ -35,6 +35,8 @@ ST_REPETITIVE = 1 << 6
 
 MAX_READ_LEN = 1024
 MAX_WIN_LEN = 8192
+NOALLOC_MAX_PAIRS = 1 << 22
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_pack_2bit",
            "mica_ctx_set_plan", "mica_ctx_last_stats", "mica_ctx_set_timing", "mica_ctx_read_timing",
@@ -42,7 +44,7 @@ EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_p
            "mica_server_now", "mica_server_submit", "mica_server_poll", "mica_server_fetch", "mica_server_stats",
            "mica_server_reset_stats", "mica_server_destroy", "mica_last_error", "mica_fm_suffix_array",
            "mica_fm_create", "mica_fm_destroy", "mica_fm_info", "mica_fm_search", "mica_pipe_create",
-           "mica_pipe_run", "mica_pipe_destroy", "mica_measure_valu_peak")
+           "mica_pipe_run", "mica_pipe_destroy", "mica_dp_align_batch_noalloc", "mica_measure_valu_peak")
 
 
 class Scoring(ctypes.Structure):
@@ -126,6 +128,8 @@ def load():
     lib.mica_ctx_destroy.restype = ctypes.c_int
     lib.mica_dp_align_batch.argtypes = [P, ctypes.POINTER(Batch), ctypes.POINTER(Scoring), u32, P]
     lib.mica_dp_align_batch.restype = ctypes.c_int
+    lib.mica_dp_align_batch_noalloc.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), u32, P]
+    lib.mica_dp_align_batch_noalloc.restype = ctypes.c_int
     lib.mica_measure_valu_peak.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]
     lib.mica_measure_valu_peak.restype = ctypes.c_int

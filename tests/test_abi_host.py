@@ -141,3 +141,22 @@ def test_fm_entry_points_reject_bad_arguments():
     assert b"out of range" in lib.mica_last_error()
     assert lib.mica_pipe_run(None, b"a.fq", b"b.sam", None) == -1
     assert lib.mica_pipe_destroy(None) == 0
+
+
+def test_noalloc_rejects_too_many_pairs_before_any_device_call():
+    """The allocation-free call refuses batches beyond its fixed workspace on
+    the host (MICA_ERR_LIMIT), and validates like the batch call."""
+    from paper_1402_4876_amd import _lib
+    lib = _lib.load()
+    s = _lib.Scoring(1, -4, 6, 1)
+    b = _lib.Batch()
+    assert lib.mica_dp_align_batch_noalloc(ctypes.byref(b), None, 0, None) == -1
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the call fails first
+    for f in ("ref2b", "win_off", "win_len", "reads2b", "read_off", "read_len", "score", "read_end", "ref_end",
+              "status"):
+        setattr(b, f, fake)
+    b.n_pairs = _lib.NOALLOC_MAX_PAIRS + 1
+    b.max_read_len, b.max_win_len = 150, 400
+    assert lib.mica_dp_align_batch_noalloc(ctypes.byref(b), ctypes.byref(s), 0, None) == -2
+    assert b"4,194,304" in lib.mica_last_error()
+    assert lib.mica_dp_align_batch_noalloc(ctypes.byref(b), ctypes.byref(s), 1 << 20, None) == -1  # flag
