@@ -1,0 +1,583 @@
+// Banded traceback (included by dp_fill.h after the value types and helpers).
+//
+// The fill computes every cell of the DP (the paper's full table, Methods,
+// "Highly parallel dynamic programming") but keeps only scores: the result
+// cell (i*, j*) and its score S.  The traceback then refills, with direction
+// bits, only a band of diagonals delta = j - i that provably holds the
+// alignment the traceback rules pick, and walks back through those bits.
+//
+// Why a band holds the path.  Every path ending at (i*, j*) with Ld deleted
+// and Li inserted bases scores at most a * (#diagonal moves) minus one gap
+// open and the extension costs; the number of diagonal moves is at most
+// min(i*, j*) and at most i* - Li.  Against the path's score (S, or S - h0
+// for an extension) that bounds Ld <= (a min(i*, j*) - S - o) / e and
+// Li <= (a i* - S - o) / (a + e), so the path stays on diagonals
+// [j* - i* - Ld, j* - i* + Li].
+//
+// Why the refill decides as the full table does.  The band DP takes the best
+// over in-band paths only, so each of its H, D and I values is at most the
+// full value; on the canonical path (all in the band) every prefix is
+// optimal, so there the values are equal.  The traceback at a path cell
+// tests the higher-priority options first: one that failed against the full
+// values (smaller than the cell's value) fails against values that are no
+// larger, and the one the full table takes holds with equal values.  16-bit
+// values that saturate at -32768 stay below every full value (the fill
+// proved the full values inside the guard band), which keeps both facts.
+//
+// Layout.  A band group of 16 lanes (one DPP row) holds two pairs packed in
+// 16-bit halves (one pair with 32-bit values); lane l of strip s holds
+// diagonal delta_lo + 16 s + l, up to 4 strips (64 diagonals).  Row by row:
+// the diagonal predecessor is in the lane, the insertion comes from the next
+// diagonal one row up (a DPP shift), and the deletion, which runs along the
+// row across lanes, is a max-plus prefix scan (max over the cells to the
+// left of H' - o - (distance) e, with H' = max(diagonal, insertion): a cell
+// whose H came from a deletion never starts a better one).  Five sign bits
+// per cell and pair are kept: diagonal loses, deletion loses, the deletion
+// of the cell to the right extends, the insertion of the cell below extends,
+// and (local) H is zero; two rows per 32-bit word per lane.
+#pragma once
+
+namespace mica {
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int o = __shfl_xor(v, d, 64);
+    v = o > v ? o : v;
+  }
+  return uni(v);
+}
+
+// DPP moves within a 16-lane row; lanes without a source keep `old`
+#define MICA_DPP(old, src, ctrl) \
+  ((T)__builtin_amdgcn_update_dpp((int)(old), (int)(src), (ctrl), 0xF, 0xF, false))
+constexpr int kDppShl1 = 0x101, kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+constexpr int kDppRor15 = 0x12F, kDppBcast15 = 0x15F;  // row_ror:15, row_newbcast:15
+
+// Per band group (or per wave for the 64-lane classes): read selectors per
+// row, then the window codes of each pair.
+template <int P, int R, int NP>
+struct BandLds {
+  static constexpr int kGroupWords = P == 64 ? kBandWords : kBandWords / 4;
+  static constexpr int kRows = P * R;
+  static constexpr int kCols = ((kGroupWords - kRows) * 4) / NP;
+  static_assert(kCols >= kRows + kBandMaxW, "window codes of the widest band fit");
+};
+
+// The banded traceback and the outputs of one work item (all lanes of the
+// wave take part).  red[] holds the fill's result per pair; sat_h[h] whether
+// pair h of this lane's fill group saturated.
+template <class V, int P, int R, int MODE>
+__device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
+                                               const MICA_GLOBAL uint32_t* __restrict__ gpairs, int npairs,
+                                               uint32_t* lds, uint8_t* slot, const bool* sat_h, int bucket) {
+  typedef typename V::T T;
+  constexpr int NP = V::kPairs;
+  constexpr int PR = P * R;
+  constexpr bool LOCAL = (MODE == 1);
+  constexpr bool EXT = (MODE == 2);
+  typedef BandLds<P, R, NP> L;
+  const int lane = threadIdx.x & 63;
+  const int bg = lane >> 4;
+  const int l = lane & 15;
+  const bool bg_ok = P == 16 || bg == 0;
+  const int sa = prm->sa, sb = prm->sb, so = prm->so, se = prm->se;
+  const int oe = so + se;
+  const MICA_GLOBAL uint32_t* __restrict__ ref2b = G(prm->ref2b);
+  const MICA_GLOBAL uint32_t* __restrict__ reads2b = G(prm->reads2b);
+  const uint32_t* red = lds + kRedOff;
+
+  // ---- per pair: result cell and band ----------------------------------------
+  int pid[NP], mm[NP], nn[NP], d0[NP], ie[NP], je[NP], scs[NP], dlo[NP], W[NP], jb[NP], h0[NP];
+  uint64_t wo[NP], ro[NP];
+  bool valid[NP], act[NP], fb[NP], sat[NP];
+  int rows_l = 0, ns_l = 0, mr_l = 0;
+#pragma unroll
+  for (int h = 0; h < NP; ++h) {
+    const int q = bg * NP + h;
+    valid[h] = bg_ok && q < npairs;
+    act[h] = fb[h] = sat[h] = false;
+    pid[h] = -1;
+    mm[h] = nn[h] = d0[h] = ie[h] = je[h] = scs[h] = h0[h] = 0;
+    dlo[h] = 0;
+    W[h] = 1;
+    jb[h] = 1;
+    wo[h] = ro[h] = 0;
+    if (valid[h]) {
+      const int p = (int)gpairs[q];
+      pid[h] = p;
+      mm[h] = G(prm->read_len)[p];
+      nn[h] = G(prm->win_len)[p];
+      wo[h] = G(prm->win_off)[p];
+      ro[h] = G(prm->read_off)[p];
+      if constexpr (EXT) h0[h] = prm->ext_h0 ? G(prm->ext_h0)[p] : prm->ext_default_h0;
+      d0[h] = EXT ? 0 : PR - mm[h];
+      scs[h] = (int)red[q * 4 + 0];
+      ie[h] = (int)red[q * 4 + 1];
+      je[h] = (int)red[q * 4 + 2];
+      sat[h] = sat_h[h];
+      if (!sat[h] && ie[h] >= 1 && je[h] >= 1) {
+        const int gain = scs[h] + d0[h] - h0[h];  // score gained over the start
+        const int ad = sa * (ie[h] < je[h] ? ie[h] : je[h]) - gain - so;
+        const int ai = sa * ie[h] - gain - so;
+        const int ld = ad >= 0 ? ad / se : 0;
+        const int li = ai >= 0 ? ai / (sa + se) : 0;
+        const int ds = je[h] - ie[h];
+        int lo = ds - ld, hi = ds + li;
+        lo = lo < -ie[h] ? -ie[h] : lo;
+        hi = hi > je[h] ? je[h] : hi;
+        dlo[h] = lo;
+        W[h] = hi - lo + 1;
+        jb[h] = lo >= 0 ? lo + 1 : 1;
+        // 16-bit: the scan's lane offsets (up to o + 16 e) must not reach
+        // the upper clamp from values up to the pair's bound
+        const long hib = EXT ? (long)h0[h] + (long)sa * (mm[h] < nn[h] ? mm[h] : nn[h])
+                             : (long)sa * (mm[h] < nn[h] ? mm[h] : nn[h]) - d0[h];
+        fb[h] = W[h] > kBandMaxW || (NP == 2 && (hib + 16L * se + so > 32767 || 16L * se + so > 32767));
+        act[h] = !fb[h];
+        if (act[h]) {
+          rows_l = ie[h] > rows_l ? ie[h] : rows_l;
+          const int ns = (W[h] + 15) >> 4;
+          ns_l = ns > ns_l ? ns : ns_l;
+          mr_l = -lo > mr_l ? -lo : mr_l;
+        }
+      }
+    }
+  }
+  const int rows_u = wave_max_int(rows_l);
+  const int ns_u = wave_max_int(ns_l);
+  const int mr_u = wave_max_int(mr_l);
+
+  // ---- codes in LDS: read selector per row, window byte per column ------------
+  uint32_t* gq = lds + (P == 64 ? 0 : bg * L::kGroupWords);
+  uint8_t* gw = (uint8_t*)(gq + L::kRows);
+  if (bg_ok && rows_u > 0) {
+    for (int i0 = l; i0 < rows_u; i0 += 16) {
+      uint32_t qs = 0;
+#pragma unroll
+      for (int h = 0; h < NP; ++h)
+        qs |= (act[h] && i0 < ie[h]) ? V::qcode(base_at(reads2b, ro[h] + (uint64_t)i0), h) : V::qdummy(h);
+      gq[i0] = qs;
+    }
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+      if (!act[h]) continue;
+      const int ncols = je[h] - jb[h] + 1;
+      for (int c = l; c < ncols; c += 16) {
+        const int j = jb[h] + c;
+        const uint32_t code = j <= nn[h] ? (uint32_t)base_at(ref2b, wo[h] + (uint64_t)(j - 1)) : 0u;
+        gw[h * L::kCols + c] = (uint8_t)(NP == 2 ? 2 * code : code);
+      }
+    }
+  }
+  lds_wait();
+
+  // ---- band refill with direction bits -----------------------------------------
+  MICA_GLOBAL uint32_t* rec = (MICA_GLOBAL uint32_t*)slot;
+  const int ns64 = ns_u * 64;
+  if (rows_u > 0) {
+    const uint32_t tab_lo = ((uint32_t)sa & 0xFFFFu) | ((uint32_t)sb << 16);
+    const uint32_t tab_hi = ((uint32_t)sb & 0xFFFFu) | ((uint32_t)sb << 16);
+    const T negv = (T)V::kNeg;
+    const T ev = V::splat(se);
+    const T oev = V::splat(oe);
+    const T cg = V::splat(l * se);
+    const T og = V::splat(so + l * se);
+    const T e16 = V::splat(16 * se);
+    T floor_v = (T)0, floor1 = (T)0;
+    if constexpr (LOCAL) {
+      if constexpr (NP == 2) {
+        floor_v = V::make2(-d0[0], -d0[1]);
+        floor1 = V::make2(1 - d0[0], 1 - d0[1]);
+      } else {
+        floor_v = (T)(-d0[0]);
+        floor1 = (T)(1 - d0[0]);
+      }
+    }
+    // row 0: H(0, j) (nothing for j < 0); the insertion candidate of the row
+    // below is H - o - e there (I(0, j) is -inf); lanes past a pair's band
+    // hold -inf so they never feed it
+    T Hd[4], Ic[4], msk[4];
+    uint32_t acc[4];
+    int wofs[NP];  // LDS byte offset of column i + delta_lo + l, less i
+#pragma unroll
+    for (int h = 0; h < NP; ++h) wofs[h] = h * L::kCols + dlo[h] + l - jb[h];
+    auto pack = [&](int v0, int v1) -> T {
+      if constexpr (NP == 2) return V::make2(v0, v1);
+      else return (T)v0;
+    };
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int hv[2] = {0, 0}, iv[2] = {0, 0};
+      bool mk[2] = {false, false}, neg[2] = {false, false};
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        const int gl = 16 * s + l;
+        const int j = dlo[h] + gl;
+        hv[h] = EXT ? (j == 0 ? h0[h] : h0[h] - (so + j * se)) : -d0[h];
+        iv[h] = hv[h] - oe;
+        neg[h] = j < 0;
+        mk[h] = act[h] && gl < W[h];
+      }
+      uint32_t nm = 0;
+      if constexpr (NP == 2) {
+        Hd[s] = V::make2(hv[0], hv[1]);
+        Ic[s] = V::make2(iv[0], iv[1]);
+        msk[s] = (mk[0] ? 0xFFFFu : 0u) | (mk[1] ? 0xFFFF0000u : 0u);
+        nm = (neg[0] ? 0xFFFFu : 0u) | (neg[1] ? 0xFFFF0000u : 0u);
+      } else {
+        Hd[s] = (T)hv[0];
+        Ic[s] = (T)iv[0];
+        msk[s] = mk[0] ? ~0u : 0u;
+        nm = neg[0] ? ~0u : 0u;
+      }
+      Hd[s] = (T)bfi(nm, (uint32_t)negv, (uint32_t)Hd[s]);
+      Ic[s] = (T)bfi(msk[s] & ~nm, (uint32_t)Ic[s], (uint32_t)negv);
+      acc[s] = 0;
+    }
+
+    auto row = [&](int i, auto par_c, auto masked_c) {
+      constexpr int PAR = decltype(par_c)::value;
+      constexpr bool MASKED = decltype(masked_c)::value;
+      const uint32_t qs = gq[i - 1];
+      T carry = negv;
+      T bnd = (T)0;
+      if constexpr (MASKED) {
+        // H(i, 0): the column-0 boundary
+        int bv[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < NP; ++h) bv[h] = LOCAL ? -d0[h] : (EXT ? h0[h] : -d0[h]) - (so + i * se);
+        bnd = pack(bv[0], bv[1]);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (s >= ns_u) break;
+        // window selector of column i + delta_lo + 16 s + l (each half its own pair)
+        uint32_t rsel;
+        {
+          int a0 = wofs[0] + i + 16 * s;
+          if (MASKED) a0 = a0 < 0 ? 0 : a0;
+          const uint32_t b0 = gw[a0];
+          if constexpr (NP == 2) {
+            int a1 = wofs[1] + i + 16 * s;
+            if (MASKED) a1 = a1 < L::kCols ? L::kCols : a1;
+            const uint32_t b1 = gw[a1];
+            rsel = __builtin_amdgcn_perm(b1, b0, 0x04040000u);
+          } else {
+            rsel = b0 * 0x01010202u;
+          }
+        }
+        const T sc = (T)__builtin_amdgcn_perm(tab_hi, tab_lo, qs ^ rsel);
+        const T x = V::add(Hd[s], sc);
+        // insertion from the next diagonal one row up
+        T old = negv;
+        if (s + 1 < 4 && s + 1 < ns_u) old = MICA_DPP(negv, Ic[s + 1 < 4 ? s + 1 : s], kDppRor15);
+        const T Iv = MICA_DPP(old, Ic[s], kDppShl1);
+        T Hp = V::vmax(x, Iv);
+        if constexpr (LOCAL) Hp = V::vmax(Hp, floor_v);
+        if constexpr (MASKED) {
+          // cells left of column 0 do not exist; column 0 is the boundary
+          uint32_t zm = 0, nm = 0;
+#pragma unroll
+          for (int h = 0; h < NP; ++h) {
+            const int j = i + dlo[h] + 16 * s + l;
+            const uint32_t half = NP == 2 ? (0xFFFFu << (16 * h)) : ~0u;
+            zm |= j == 0 ? half : 0u;
+            nm |= j < 0 ? half : 0u;
+          }
+          Hp = (T)bfi(zm, (uint32_t)bnd, (uint32_t)Hp);
+          Hp = (T)bfi(nm, (uint32_t)negv, (uint32_t)Hp);
+        }
+        // deletion: exclusive max-plus prefix over the row (strip-relative
+        // offsets; `carry` brings the strips to the left)
+        T g = V::add(Hp, cg);
+        g = V::vmax(g, MICA_DPP(negv, g, kDppShr1));
+        g = V::vmax(g, MICA_DPP(negv, g, kDppShr2));
+        g = V::vmax(g, MICA_DPP(negv, g, kDppShr4));
+        g = V::vmax(g, MICA_DPP(negv, g, kDppShr8));
+        if (s > 0) g = V::vmax(g, carry);
+        const T excl = MICA_DPP(carry, g, kDppShr1);
+        const T Dv = V::sub(excl, og);
+        if (s + 1 < ns_u) carry = V::sub(MICA_DPP(negv, g, kDppBcast15), e16);
+        const T Hv = V::vmax(Hp, Dv);
+        const T Tv = V::sub(Hv, oev);
+        const T Icn = V::vmax(V::sub(Iv, ev), Tv);
+        // sign bits: diagonal loses, deletion loses | deletion of the right
+        // cell extends, insertion of the cell below extends | H is zero
+        const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)V::sub(Dv, Hv), (uint32_t)V::sub(x, Hv), V::kSignSel);
+        const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)V::sub(Tv, Icn), (uint32_t)V::sub(Tv, V::sub(Dv, ev)),
+                                                   V::kSignSel);
+        constexpr uint32_t M0 = 0x01010101u << (4 * PAR), M1 = 0x02020202u << (4 * PAR),
+                           M2 = 0x04040404u << (4 * PAR);
+        uint32_t a = acc[s];
+        a = (p01 & M0) | a;
+        a = (p23 & M1) | a;
+        if constexpr (LOCAL) {
+          const uint32_t zr = (uint32_t)V::sub(Hv, floor1);
+          a = (__builtin_amdgcn_perm(zr, zr, V::kSignSel) & M2) | a;
+        }
+        acc[s] = a;
+        Hd[s] = Hv;
+        Ic[s] = (T)bfi(msk[s], (uint32_t)Icn, (uint32_t)negv);
+      }
+    };
+    auto flush = [&](int i) {  // rows i and i + 1 (1-based i odd)
+      const size_t base = (size_t)((i - 1) >> 1) * (size_t)ns64 + (size_t)lane;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (s >= ns_u) break;
+        rec[base + (size_t)(s * 64)] = acc[s];
+        acc[s] = 0;
+      }
+    };
+    int i = 1;
+    for (; i <= rows_u && i <= mr_u; i += 2) {
+      row(i, std::integral_constant<int, 0>{}, std::true_type{});
+      if (i + 1 <= rows_u) row(i + 1, std::integral_constant<int, 1>{}, std::true_type{});
+      flush(i);
+    }
+    for (; i + 1 <= rows_u; i += 2) {
+      row(i, std::integral_constant<int, 0>{}, std::false_type{});
+      row(i + 1, std::integral_constant<int, 1>{}, std::false_type{});
+      flush(i);
+    }
+    if (i <= rows_u) {
+      row(i, std::integral_constant<int, 0>{}, std::false_type{});
+      flush(i);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  lds_wait();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+  // ---- outputs and the walk -------------------------------------------------------
+  // X = 16 / NP lanes of a band group walk pair h together (see the walk of
+  // the full traceback); every lane holds the walk state.
+  constexpr int X = 16 / NP;
+  const int h = l / X;
+  const int x = l - h * X;
+  int my = 0;  // index of this lane's pair among the halves
+#pragma unroll
+  for (int k = 0; k < NP; ++k) my = (k == h) ? k : my;
+  auto pick = [&](const int* v) -> int {
+    int r = v[0];
+#pragma unroll
+    for (int k = 1; k < NP; ++k) r = my == k ? v[k] : r;
+    return r;
+  };
+  bool v_ = valid[0], s_ = sat[0], f_ = fb[0];
+  uint64_t wo_ = wo[0], ro_ = ro[0];
+#pragma unroll
+  for (int k = 1; k < NP; ++k)
+    if (my == k) {
+      v_ = valid[k];
+      s_ = sat[k];
+      f_ = fb[k];
+      wo_ = wo[k];
+      ro_ = ro[k];
+    }
+  (void)wo_;
+  (void)ro_;
+  if (v_) {
+    const int p_ = pick(pid), m_ = pick(mm), n_ = pick(nn), d0_ = pick(d0);
+    const int q = bg * NP + h;
+    if (s_) {
+      if (x == 0) {
+        const uint32_t pos = atomicAdd(&prm->counters[kCtrRerun], 1u);
+        G(prm->rerun)[pos] = (uint32_t)p_;
+      }
+    } else if (f_) {
+      if (x == 0) {
+        const uint32_t pos = atomicAdd(&prm->fbcount[bucket], 1u);
+        G(prm->fbsorted)[G(prm->bstart)[bucket] + pos] = (uint32_t)p_;
+      }
+    } else {
+      const int score = pick(scs) + d0_;
+      const int ie_ = pick(ie), je_ = pick(je), dlo_ = pick(dlo), W_ = pick(W);
+      if (x == 0) {
+        G(prm->score)[p_] = score;
+        G(prm->read_end)[p_] = ie_;
+        G(prm->ref_end)[p_] = je_;
+      }
+      uint32_t st = 0;
+      MICA_GLOBAL uint32_t* stg =
+          (MICA_GLOBAL uint32_t*)(slot + prm->dir_bytes) + (size_t)q * (size_t)prm->stage_stride;
+      int i = ie_, j = je_;
+      int state = 0;  // 0: H, 1: D, 2: I
+      int nruns = 0, cur_op = -1, cur_len = 0;
+      bool bad = ie_ < 0 || ie_ > m_ || je_ < 0 || je_ > n_;
+      const int lane0 = lane - x;
+      constexpr uint64_t xmask = (1ull << X) - 1;
+      auto sub = [&](bool pr) -> uint64_t { return (__ballot(pr) >> lane0) & xmask; };
+      auto first_clear = [&](uint64_t msk) -> int {
+        const uint64_t z = ~msk & xmask;
+        return z ? (int)__builtin_ctzll(z) : X;
+      };
+      constexpr int C = 64 / X;
+      constexpr int XC = X * C;
+      auto first_clear_xc = [&](uint64_t msk) -> int {
+        const uint64_t z = ~msk;
+        return z ? (int)__builtin_ctzll(z) : XC;
+      };
+      // the record word of cell (ii, jj) (1 <= ii, inside the band) and the
+      // bit offset of its row and pair half; kinds: +0 diagonal loses
+      // (second half-word: deletion loses), +1 deletion of the right cell
+      // extends (second: insertion of the cell below extends), +2 zero
+      auto in_band = [&](int ii, int jj) -> bool {
+        const int gl = jj - ii - dlo_;
+        return ii >= 1 && gl >= 0 && gl < W_;
+      };
+      auto word = [&](int ii, int jj, int* bit) -> uint32_t {
+        const int gl = jj - ii - dlo_;
+        *bit = 8 * h + 4 * ((ii - 1) & 1);
+        return rec[(size_t)((ii - 1) >> 1) * (size_t)ns64 + (size_t)((gl >> 4) * 64 + bg * 16 + (gl & 15))];
+      };
+      auto emit = [&](int op, int len) {
+        if (op == cur_op) {
+          cur_len += len;
+        } else {
+          if (cur_len > 0) {
+            if (x == 0) stg[nruns] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
+            ++nruns;
+          }
+          cur_op = op;
+          cur_len = len;
+        }
+      };
+      while (!bad) {
+        if (state == 0) {
+          if (i == 0) {
+            if (EXT && j > 0) {  // an extension starts at the anchor: a leading deletion
+              emit(2, j);
+              j = 0;
+            }
+            break;
+          }
+          if (j == 0) {
+            if (LOCAL) break;
+            emit(1, i);  // a leading insertion (semi-global, extension)
+            i = 0;
+            break;
+          }
+          if (i > m_ || j > n_ || !in_band(i, j)) {
+            bad = true;
+            break;
+          }
+          if (LOCAL) {
+            int bit;
+            const uint32_t w = word(i, j, &bit);
+            if ((w >> (bit + 2)) & 1u) break;  // H = 0: the local alignment starts here
+          }
+          // lane x: the diagonal cells c = x + X * cc, (i - c, j - c), all on
+          // this lane's diagonal of the band
+          uint64_t good = 0, turn = 0, dl = 0;
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc) {
+            const int c = x + X * cc;
+            const int ic = i - c, jc = j - c;
+            const bool in = ic >= 1 && jc >= 1;
+            bool diag = false, dlose = false, zero = false;
+            if (in) {
+              int bit;
+              const uint32_t w = word(ic, jc, &bit);
+              diag = ((w >> bit) & 1u) == 0;
+              dlose = ((w >> (bit + 16)) & 1u) != 0;
+              zero = LOCAL && ((w >> (bit + 2)) & 1u) != 0;
+            }
+            good |= sub(in && diag && !zero) << (X * cc);
+            turn |= sub(in && !diag && !zero) << (X * cc);
+            dl |= sub(dlose) << (X * cc);
+          }
+          const int Lr = first_clear_xc(good);
+          if (Lr > 0) {
+            emit(0, Lr);
+            i -= Lr;
+            j -= Lr;
+          }
+          // a cell that turns into a gap sets the state here; boundaries,
+          // range and the zero stop are left to the next iteration
+          if (Lr < XC && ((turn >> Lr) & 1u)) state = ((dl >> Lr) & 1u) ? 2 : 1;
+          continue;
+        }
+        if (i < 1 || j < 1 || i > m_ || j > n_) {
+          bad = true;
+          break;
+        }
+        if (state == 1) {
+          // a deletion along row i: cell (i, j - x) extends when the bit its
+          // left neighbour keeps says so; at column 1 a deletion can only open
+          const int jc = j - x;
+          bool ext = false;
+          if (jc >= 2 && in_band(i, jc - 1)) {
+            int bit;
+            const uint32_t w = word(i, jc - 1, &bit);
+            ext = ((w >> (bit + 1)) & 1u) != 0;
+          }
+          const int ones = first_clear(sub(ext));
+          if (ones < X) {  // cells 0..ones-1 extend, cell `ones` opens
+            emit(2, ones + 1);
+            j -= ones + 1;
+            state = 0;
+          } else {
+            emit(2, X);
+            j -= X;
+          }
+        } else {
+          // an insertion up column j: cell (i - x, j) extends when the bit of
+          // the cell above says so; at row 1 an insertion can only open
+          const int ic = i - x;
+          const bool in = ic >= 1;
+          bool ext = false;
+          if (ic >= 2 && in_band(ic - 1, j)) {
+            int bit;
+            const uint32_t w = word(ic - 1, j, &bit);
+            ext = ((w >> (bit + 17)) & 1u) != 0;
+          }
+          const int ones = first_clear(sub(ext));
+          const uint64_t inm = sub(in);
+          if (ones < X && ((inm >> ones) & 1u)) {
+            emit(1, ones + 1);
+            i -= ones + 1;
+            state = 0;
+          } else {
+            // X extensions, or a run that would leave the matrix (flagged
+            // by the range check of the next iteration)
+            emit(1, ones);
+            i -= ones;
+          }
+        }
+      }
+      if (cur_len > 0) {
+        if (x == 0) stg[nruns] = ((uint32_t)cur_len << 4) | (uint32_t)cur_op;
+        ++nruns;
+      }
+      if (bad) {
+        st |= kStInternal;
+        i = j = 0;
+        nruns = 0;
+      }
+      if (x == 0) {
+        if (prm->flags & (kOutStart | kOutCigar)) {
+          G(prm->read_start)[p_] = i;
+          G(prm->ref_start)[p_] = j;
+        }
+        if (prm->flags & kOutCigar) {
+          const int cap = prm->cigar_cap;
+          MICA_GLOBAL uint32_t* out = G(prm->cigar) + (size_t)p_ * (size_t)cap;
+          const int ncopy = nruns < cap ? nruns : cap;
+          for (int y = 0; y < ncopy; ++y) out[y] = stg[nruns - 1 - y];
+          if (nruns > cap) {
+            st |= kStCigarTrunc;
+            G(prm->n_cigar)[p_] = -nruns;
+          } else {
+            G(prm->n_cigar)[p_] = nruns;
+          }
+        }
+        G(prm->status)[p_] = st;
+      }
+    }
+  }
+  lds_wait();
+}
+
+}  // namespace mica

@@ -39,7 +39,9 @@ constexpr size_t kCounters = 4 * kNumBuckets + 8;
 constexpr size_t kBhead = 4 * kNumBuckets + 8 + kNumCounters;
 constexpr size_t kScount = 5 * kNumBuckets + 8 + kNumCounters;
 constexpr size_t kSfill = kScount + kNumSubBuckets;
-constexpr size_t kWords = kSfill + kNumSubBuckets;
+constexpr size_t kFbcount = kSfill + kNumSubBuckets;
+constexpr size_t kFbhead = kFbcount + kNumBuckets;
+constexpr size_t kWords = kFbhead + kNumBuckets;
 }  // namespace small
 
 // Work-queue order of the buckets (persistent parts first, each by
@@ -53,7 +55,9 @@ mica_status_t check_batch(const mica_batch_t* b, const mica_scoring_t* s, uint32
 
 // The fill launches of a batch, in launch order, and the resident blocks per
 // CU of each (its occupancy at the library's block shape).
-constexpr int kMaxFills = 2 * kNumModes + kNumBuckets + 1;
+constexpr int kMaxFills = 2 * kNumModes + 2 * kNumBuckets + 1;
+// per-pair work lists of a batch: bucket_of | sorted | rerun | fbsorted
+constexpr int kPairLists = 4;
 struct FillPlan {
   KernelFn fn[kMaxFills];
   int occ[kMaxFills];

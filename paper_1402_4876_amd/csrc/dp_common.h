@@ -104,13 +104,23 @@ constexpr uint32_t kOutStart = 1u << 0;
 constexpr uint32_t kOutCigar = 1u << 1;
 constexpr uint32_t kForceInt32 = 1u << 8;
 
-// LDS per wave (32-bit words): a window-selector ring of 256 columns for each
-// of up to 4 lane groups, plus a reduction area.
+// LDS per wave (32-bit words): during the fill, a window-selector ring of 256
+// columns for each of up to 4 lane groups and the per-lane local-best
+// candidates; after it, the banded traceback's read and window codes in the
+// same space.  The per-pair results (shifted score, i*, j*) and the
+// extension's end-to-end candidates sit at the top.
 constexpr int kRing = 256;
 constexpr int kRingWords = 4 * kRing;
-constexpr int kRedWords = 64 * 2 * 4;
-constexpr int kLdsWaveWords = kRingWords + kRedWords;
+constexpr int kCandWords = 64 * 2 * 3;
+constexpr int kLdsWaveWords = 2048;
+constexpr int kRedOff = kLdsWaveWords - 64;  // 8 pairs x 4 words
+constexpr int kGslOff = kLdsWaveWords - 32;  // 8 pairs x 2 words
+constexpr int kBandWords = kRedOff;          // band codes: [0, kRedOff)
+static_assert(kRingWords + kCandWords <= kRedOff, "fill areas below the results");
 constexpr int kWavesPerBlock = 4;
+// widest band of the banded traceback (diagonals); wider pairs are traced
+// back from a full fill of direction bits instead
+constexpr int kBandMaxW = 64;
 
 struct Params {
   // batch (device pointers owned by the caller)
@@ -155,6 +165,9 @@ struct Params {
   const uint8_t* class_of_m;   // [kMaxM + 1]
   uint32_t* counters;          // [kNumCounters]
   uint32_t* bhead;             // [kNumBuckets] next work item of each plain bucket launch
+  uint32_t* fbcount;           // [kNumBuckets] pairs whose band was too wide, per bucket
+  uint32_t* fbhead;            // [kNumBuckets] next work item of each fallback launch
+  uint32_t* fbsorted;          // [n_pairs] those pairs, in their bucket's range of `sorted`
   uint8_t* scratch;            // n_slots * slot_bytes
   uint64_t slot_bytes;         // per resident wave: direction bits + CIGAR staging
   uint64_t dir_bytes;          // direction-bit part of a slot
@@ -170,6 +183,7 @@ typedef void (*KernelFn)(const Params*);
 // Kernel entry points of the library, indexed for the host runtime.
 struct KernelTable {
   KernelFn bucket[2][kNumBuckets];  // [with traceback][bucket]
+  KernelFn fallback[kNumBuckets];   // full direction-bit traceback of wide-band pairs
   KernelFn persistent[2][kNumModes][2];  // [with traceback][mode][class part]
   KernelFn rerun[2];
   KernelFn zero, plan, scan, scatter;

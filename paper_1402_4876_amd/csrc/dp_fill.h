@@ -168,7 +168,9 @@ __device__ __forceinline__ int base_at(const MICA_GLOBAL uint32_t* __restrict__ 
 // one wave more: their step loops still do not spill, their set-up and walk
 // do, and the extra wave hides more latency than those spills cost
 // (measured on the 10-row kernels: +1.8% semi-global, +0.8% local).
-__host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool dir) {
+__host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, int tb) {
+  // the banded traceback's fill keeps no direction bits: the score-only budget
+  const bool dir = tb == 2;
   const int r = class_rows(cls);
   if (class_lanes(cls) == 64 && r == 16) return 2;
   if (kind == kK32) {
@@ -199,8 +201,8 @@ __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, bool d
 // hides more of the latency of set-up and walk than the spills cost
 // (measured: +4% on 10^6 seed extensions, +4-5% on the mixed-length batch,
 // against the lower budgets).
-__host__ __device__ constexpr int persist_waves(bool dir, int mode, int part) {
-  return mode == 0 ? (dir ? 4 : 3) : (part == 0 ? 4 : 3);
+__host__ __device__ constexpr int persist_waves(int tb, int mode, int part) {
+  return tb ? 4 : (mode == 0 ? 3 : (part == 0 ? 4 : 3));
 }
 
 // Lanes of one wave exchange values through LDS: LDS operations of a wave
@@ -213,12 +215,25 @@ __device__ __forceinline__ void lds_wait() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+}  // namespace mica
+
+#include "band.h"
+
+namespace mica {
+
+// Traceback kinds of a fill kernel: none (score and end cell only), banded
+// (score-only fill, then the band refill and walk of band.h), or full
+// (direction bits of every cell stored during the fill; the fallback for
+// pairs whose band is too wide, and the 32-bit re-run).
+enum Traceback : int { kTbNone = 0, kTbBand = 1, kTbFull = 2 };
+
 // One wave-sized work item: G = 64/P groups, each aligning kPairs pairs.
-template <class V, int P, int R, int MODE, bool DIR, bool SAT>
+template <class V, int P, int R, int MODE, int TB, bool SAT>
 __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
                                           const uint32_t* __restrict__ pairs, int npairs,
-                                          uint32_t* lds, uint8_t* slot) {
+                                          uint32_t* lds, uint8_t* slot, int bucket) {
   typedef typename V::T T;
+  constexpr bool DIR = (TB == kTbFull);
   constexpr int NP = V::kPairs;
   constexpr int PR = P * R;
   constexpr bool LOCAL = (MODE == 1);
@@ -361,8 +376,8 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   }
 
   uint32_t* ring = lds + g * kRing;
-  uint32_t* red = lds + kRingWords + 64 * 2 * 3;  // final (score, i*, j*) per pair
-  uint32_t* cand = lds + kRingWords;              // per-lane local candidates
+  uint32_t* red = lds + kRedOff;     // final (score, i*, j*) per pair
+  uint32_t* cand = lds + kRingWords;  // per-lane local candidates
   // direction words per lane and step
   constexpr int NW = R <= 8 ? 2 : 4;
   MICA_GLOBAL u32x4* dir4 = (MICA_GLOBAL u32x4*)slot;
@@ -559,7 +574,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     // the start cell (0,0) is worth 0 (local, shifted by -d0) or h0
     // (extension).  An extension's lane holding row m also leaves that row's
     // best (the end-to-end candidate) in gsl.
-    uint32_t* gsl = red + 64;
+    uint32_t* gsl = lds + kGslOff;
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
       int b0 = EXT ? h0[h] : -d0[h], c0 = 0, i0 = 0;
@@ -647,6 +662,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     }
   }
   lds_wait();
+  if constexpr (TB == kTbBand) {
+    band_traceback<V, P, R, MODE>(prm, gpairs, npairs, lds, slot, sat_h, bucket);
+    return;
+  }
   if constexpr (DIR) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
 
   // ---- outputs and traceback ---------------------------------------------------
@@ -920,23 +939,23 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 // ----------------------------------------------------------------------------
 // dispatch of (kind, class, mode) to the specialised item function
 
-template <bool DIR, int CLS, int KIND, int MODE>
+template <int TB, int CLS, int KIND, int MODE>
 __device__ __forceinline__ void run_one(const Params* prm, const uint32_t* pairs, int np,
-                                        uint32_t* lds, uint8_t* slot) {
+                                        uint32_t* lds, uint8_t* slot, int bucket) {
   constexpr int P = class_lanes(CLS);
   constexpr int R = class_rows(CLS);
   if constexpr (KIND == kK32)
-    process_item<V32, P, R, MODE, DIR, false>(prm, pairs, np, lds, slot);
+    process_item<V32, P, R, MODE, TB, false>(prm, pairs, np, lds, slot, bucket);
   else
-    process_item<V16, P, R, MODE, DIR, KIND == kK16Sat>(prm, pairs, np, lds, slot);
+    process_item<V16, P, R, MODE, TB, KIND == kK16Sat>(prm, pairs, np, lds, slot, bucket);
 }
 
-template <bool DIR, int MODE, int CLS, int CHI>
+template <int TB, int MODE, int CLS, int CHI>
 __device__ __forceinline__ void dispatch(int bucket, const Params* prm, const uint32_t* pairs, int np,
                                          uint32_t* lds, uint8_t* slot) {
   if constexpr (CLS <= CHI) {
-    if (bucket_class(bucket) == CLS) run_one<DIR, CLS, kK16, MODE>(prm, pairs, np, lds, slot);
-    else dispatch<DIR, MODE, CLS + 1, CHI>(bucket, prm, pairs, np, lds, slot);
+    if (bucket_class(bucket) == CLS) run_one<TB, CLS, kK16, MODE>(prm, pairs, np, lds, slot, bucket);
+    else dispatch<TB, MODE, CLS + 1, CHI>(bucket, prm, pairs, np, lds, slot);
   }
 }
 
@@ -945,8 +964,8 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_
 // Persistent launch (one per mode and class part): every resident wave takes
 // work items from its part of the queue (buckets in descending cost order)
 // until it is empty.
-template <bool DIR, int MODE, int PART>
-__global__ __launch_bounds__(256, persist_waves(DIR, MODE, PART)) void
+template <int TB, int MODE, int PART>
+__global__ __launch_bounds__(256, persist_waves(TB, MODE, PART)) void
 k_fill_persistent(const Params* __restrict__ prm) {
   constexpr int QP = persist_queue_part(MODE, PART);
   constexpr int CLO = PART == 0 ? 0 : kPersistSmallMax + 1;
@@ -981,13 +1000,18 @@ k_fill_persistent(const Params* __restrict__ prm) {
     const uint32_t first = idx * (uint32_t)ppi;
     const uint32_t cnt = G(prm->bcount)[bucket];
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    dispatch<DIR, MODE, CLO, CHI>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
+    dispatch<TB, MODE, CLO, CHI>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
   }
 }
 
-// Plain launch: one bucket per kernel, waves stride over its items.
-template <bool DIR, int KIND, int CLS, int MODE>
-__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, DIR)) void k_fill_bucket(const Params* __restrict__ prm) {
+// Waves of a plain launch take the items of one pair list (a bucket, or the
+// bucket's pairs sent back for the full traceback) from a queue head (items
+// differ in cost: window lengths and traceback paths vary).  Any number of
+// waves drains the queue, so waves beyond the item count leave at once
+// rather than contend for the head (an empty list then costs its launch only).
+template <int TB, int KIND, int CLS, int MODE>
+__device__ __forceinline__ void drain_list(const Params* __restrict__ prm, const uint32_t* base, uint32_t cnt,
+                                           uint32_t* head) {
   extern __shared__ uint32_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
   const int slot_id = blockIdx.x * kWavesPerBlock + wave;
@@ -996,28 +1020,43 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, DIR)) void 
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
   constexpr int bucket = bucket_id(KIND, CLS, MODE);
   constexpr int ppi = pairs_per_item(KIND, CLS);
-  const uint32_t cnt = G(prm->bcount)[bucket];
   const uint32_t items = (cnt + ppi - 1) / ppi;
-  const uint32_t* base = prm->sorted + G(prm->bstart)[bucket];
-  // waves take the bucket's items from a queue head (items differ in cost:
-  // window lengths and traceback paths vary).  Any number of waves drains
-  // the queue, so waves beyond the item count leave at once rather than
-  // contend for the head (an empty bucket then costs its launch only).
   if ((uint32_t)slot_id >= items) return;
   for (;;) {
     uint32_t v = 0;
-    if ((threadIdx.x & 63) == 0) v = atomicAdd(&prm->bhead[bucket], 1u);
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(head, 1u);
     const uint32_t it = wave_uniform(v);
     if (it >= items) break;
     const uint32_t first = it * ppi;
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    run_one<DIR, CLS, KIND, MODE>(prm, base + first, np, lds, slot);
+    run_one<TB, CLS, KIND, MODE>(prm, base + first, np, lds, slot, bucket);
   }
 }
 
-template <bool DIR, int KIND, int MODE, int... CLS>
+// Plain launch: one bucket per kernel.
+template <int TB, int KIND, int CLS, int MODE>
+__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, TB)) void k_fill_bucket(const Params* __restrict__ prm) {
+  constexpr int bucket = bucket_id(KIND, CLS, MODE);
+  drain_list<TB, KIND, CLS, MODE>(prm, prm->sorted + G(prm->bstart)[bucket], G(prm->bcount)[bucket],
+                                  &prm->bhead[bucket]);
+}
+
+// Full traceback of the pairs of one bucket whose band was too wide (after
+// every banded fill launch).
+template <int KIND, int CLS, int MODE>
+__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) void k_fill_fallback(const Params* __restrict__ prm) {
+  constexpr int bucket = bucket_id(KIND, CLS, MODE);
+  drain_list<kTbFull, KIND, CLS, MODE>(prm, prm->fbsorted + G(prm->bstart)[bucket], G(prm->fbcount)[bucket],
+                                       &prm->fbhead[bucket]);
+}
+
+template <int TB, int KIND, int MODE, int... CLS>
 void fill_bucket_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
-  ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_bucket<DIR, KIND, CLS, MODE>), ...);
+  ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_bucket<TB, KIND, CLS, MODE>), ...);
+}
+template <int KIND, int MODE, int... CLS>
+void fill_fallback_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
+  ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_fallback<KIND, CLS, MODE>), ...);
 }
 using ClassSeq = std::make_integer_sequence<int, kNumClasses>;
 

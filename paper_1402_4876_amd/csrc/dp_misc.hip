@@ -20,9 +20,11 @@ __global__ __launch_bounds__(256) void k_rerun(const Params* __restrict__ prm) {
     const uint32_t* pp = prm->rerun + it;
     const int p = (int)*pp;
     const int md = prm->mode ? prm->mode[p] : prm->default_mode;
-    if (md == 2) process_item<V32, 64, 16, 2, DIR, false>(prm, pp, 1, lds, slot);
-    else if (md == 1) process_item<V32, 64, 16, 1, DIR, false>(prm, pp, 1, lds, slot);
-    else process_item<V32, 64, 16, 0, DIR, false>(prm, pp, 1, lds, slot);
+    // a full traceback: the re-run is rare and needs no band
+    constexpr int TB = DIR ? kTbFull : kTbNone;
+    if (md == 2) process_item<V32, 64, 16, 2, TB, false>(prm, pp, 1, lds, slot, -1);
+    else if (md == 1) process_item<V32, 64, 16, 1, TB, false>(prm, pp, 1, lds, slot, -1);
+    else process_item<V32, 64, 16, 0, TB, false>(prm, pp, 1, lds, slot, -1);
     if ((threadIdx.x & 63) == 0) prm->status[p] |= kStSaturated;
   }
 }
@@ -33,7 +35,11 @@ __global__ __launch_bounds__(256) void k_rerun(const Params* __restrict__ prm) {
 __global__ void k_zero(const Params* __restrict__ prm) {
   for (int i = threadIdx.x; i < kNumSubBuckets; i += blockDim.x) prm->scount[i] = 0;
   const int i = threadIdx.x;
-  if (i < kNumBuckets) prm->bhead[i] = 0;
+  if (i < kNumBuckets) {
+    prm->bhead[i] = 0;
+    prm->fbcount[i] = 0;
+    prm->fbhead[i] = 0;
+  }
   if (i < kNumCounters) prm->counters[i] = 0;
 }
 
@@ -238,6 +244,9 @@ namespace mica {
   X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1) \
   X(k16, 2, 0) X(k16, 2, 1) X(k16s, 2, 0) X(k16s, 2, 1) X(k32, 2, 0) X(k32, 2, 1)
 MICA_FILL_ALL(MICA_FILL_DECL)
+#define MICA_FB_ALL(X) X(k16, 0) X(k16, 1) X(k16, 2) X(k16s, 0) X(k16s, 1) X(k16s, 2) X(k32, 0) X(k32, 1) X(k32, 2)
+#define MICA_FB_DECL(kind, mode) void reg_fill_fb_##kind##_##mode(KernelTable& t);
+MICA_FB_ALL(MICA_FB_DECL)
 #define MICA_PERSIST_ALL(X) \
   X(0, 0, 0) X(0, 0, 1) X(0, 1, 0) X(0, 1, 1) X(0, 2, 0) X(0, 2, 1) \
   X(1, 0, 0) X(1, 0, 1) X(1, 1, 0) X(1, 1, 1) X(1, 2, 0) X(1, 2, 1)
@@ -247,6 +256,8 @@ MICA_PERSIST_ALL(MICA_PERSIST_DECL)
 KernelTable::KernelTable() {
 #define MICA_FILL_CALL(kind, mode, dir) reg_fill_##kind##_##mode##_##dir(*this);
   MICA_FILL_ALL(MICA_FILL_CALL)
+#define MICA_FB_CALL(kind, mode) reg_fill_fb_##kind##_##mode(*this);
+  MICA_FB_ALL(MICA_FB_CALL)
 #define MICA_PERSIST_CALL(dir, mode, part) reg_persistent_##dir##_##mode##_##part(*this);
   MICA_PERSIST_ALL(MICA_PERSIST_CALL)
   rerun[0] = &k_rerun<false>;

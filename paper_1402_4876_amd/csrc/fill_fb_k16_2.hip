@@ -1,0 +1,8 @@
+// Full-traceback fill kernels for pairs whose band was too wide: packed 16-bit scores, seed extension.
+#include "dp_fill.h"
+
+namespace mica {
+void reg_fill_fb_k16_2(KernelTable& t) {
+  fill_fallback_table<kK16, 2>(t.fallback, ClassSeq{});
+}
+}  // namespace mica

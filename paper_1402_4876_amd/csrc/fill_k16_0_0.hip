@@ -1,8 +1,8 @@
-// Per-bucket fill kernels: packed 16-bit scores, semi-global, score and end only.
+// Per-bucket fill kernels: packed 16-bit scores, semi-global, score and end cell only.
 #include "dp_fill.h"
 
 namespace mica {
 void reg_fill_k16_0_0(KernelTable& t) {
-  fill_bucket_table<false, kK16, 0>(t.bucket[0], ClassSeq{});
+  fill_bucket_table<kTbNone, kK16, 0>(t.bucket[0], ClassSeq{});
 }
 }  // namespace mica

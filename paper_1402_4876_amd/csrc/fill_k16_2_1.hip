@@ -1,8 +1,8 @@
-// Per-bucket fill kernels: packed 16-bit scores, seed extension, with traceback.
+// Per-bucket fill kernels: packed 16-bit scores, seed extension, with the banded traceback.
 #include "dp_fill.h"
 
 namespace mica {
 void reg_fill_k16_2_1(KernelTable& t) {
-  fill_bucket_table<true, kK16, 2>(t.bucket[1], ClassSeq{});
+  fill_bucket_table<kTbBand, kK16, 2>(t.bucket[1], ClassSeq{});
 }
 }  // namespace mica

@@ -1,8 +1,8 @@
-// Per-bucket fill kernels: packed 16-bit scores with saturation check, semi-global, score and end only.
+// Per-bucket fill kernels: packed 16-bit scores with a saturation check, semi-global, score and end cell only.
 #include "dp_fill.h"
 
 namespace mica {
 void reg_fill_k16s_0_0(KernelTable& t) {
-  fill_bucket_table<false, kK16Sat, 0>(t.bucket[0], ClassSeq{});
+  fill_bucket_table<kTbNone, kK16Sat, 0>(t.bucket[0], ClassSeq{});
 }
 }  // namespace mica

@@ -1,8 +1,8 @@
-// Per-bucket fill kernels: packed 16-bit scores with a saturation check, seed extension, with traceback.
+// Per-bucket fill kernels: packed 16-bit scores with a saturation check, seed extension, with the banded traceback.
 #include "dp_fill.h"
 
 namespace mica {
 void reg_fill_k16s_2_1(KernelTable& t) {
-  fill_bucket_table<true, kK16Sat, 2>(t.bucket[1], ClassSeq{});
+  fill_bucket_table<kTbBand, kK16Sat, 2>(t.bucket[1], ClassSeq{});
 }
 }  // namespace mica

@@ -28,8 +28,8 @@ constexpr size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 constexpr size_t kOffParams = 0;
 constexpr size_t kOffSmall = kOffParams + al256(sizeof(Params));
 constexpr size_t kOffClass = kOffSmall + al256(small::kWords * 4);
-constexpr size_t kOffPairs = kOffClass + al256(kMaxM + 1);         // bucket_of | sorted | rerun
-constexpr size_t kOffSlots = kOffPairs + al256((size_t)3 * kMaxPairs * 4);  // traceback slots
+constexpr size_t kOffPairs = kOffClass + al256(kMaxM + 1);  // bucket_of | sorted | rerun | fbsorted
+constexpr size_t kOffSlots = kOffPairs + al256((size_t)kPairLists * kMaxPairs * 4);  // traceback slots
 static_assert(kOffSlots + (size_t(64) << 20) <= kScratchBytes, "room for the traceback slots");
 static_assert(sizeof(Params) % 4 == 0, "parameter block copied as words");
 
@@ -134,6 +134,9 @@ mica_status_t mica_dp_align_batch_noalloc(const mica_batch_t* b, const mica_scor
   P.bucket_of = pairs;
   P.sorted = pairs + kMaxPairs;
   P.rerun = pairs + 2 * kMaxPairs;
+  P.fbsorted = pairs + 3 * kMaxPairs;
+  P.fbcount = sm + small::kFbcount;
+  P.fbhead = sm + small::kFbhead;
   P.bcount = sm + small::kBcount;
   P.bstart = sm + small::kBstart;
   P.scount = sm + small::kScount;

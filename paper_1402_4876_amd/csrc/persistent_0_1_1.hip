@@ -1,6 +1,6 @@
-// Persistent fill kernel: score and end only, local, reads of 161 to 256 bases.
+// Persistent fill kernel: score and end cell only, local, reads of 161-256 bases.
 #include "dp_fill.h"
 
 namespace mica {
-void reg_persistent_0_1_1(KernelTable& t) { t.persistent[0][1][1] = &k_fill_persistent<false, 1, 1>; }
+void reg_persistent_0_1_1(KernelTable& t) { t.persistent[0][1][1] = &k_fill_persistent<kTbNone, 1, 1>; }
 }  // namespace mica

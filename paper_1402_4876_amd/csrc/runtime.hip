@@ -59,6 +59,8 @@ uint32_t* small_counters(mica_ctx* c) { return c->d_small + small::kCounters; }
 uint32_t* small_bhead(mica_ctx* c) { return c->d_small + small::kBhead; }
 uint32_t* small_scount(mica_ctx* c) { return c->d_small + small::kScount; }
 uint32_t* small_sfill(mica_ctx* c) { return c->d_small + small::kSfill; }
+uint32_t* small_fbcount(mica_ctx* c) { return c->d_small + small::kFbcount; }
+uint32_t* small_fbhead(mica_ctx* c) { return c->d_small + small::kFbhead; }
 constexpr size_t kSmallWords = small::kWords;
 
 // cost of one work item of a bucket, for the descending work-queue order
@@ -90,7 +92,7 @@ mica_status_t ensure_pairs(mica_ctx* c, int64_t n) {
   if (c->d_pairs) HIP_TRY(hipFree(c->d_pairs));
   c->d_pairs = nullptr;
   const int64_t cap = std::max<int64_t>(n, 1024);
-  if (hipMalloc(&c->d_pairs, (size_t)cap * 3 * sizeof(uint32_t)) != hipSuccess) {
+  if (hipMalloc(&c->d_pairs, (size_t)cap * kPairLists * sizeof(uint32_t)) != hipSuccess) {
     c->pair_cap = 0;
     return fail(MICA_ERR_OUT_OF_MEMORY, "cannot allocate per-pair workspace");
   }
@@ -344,6 +346,19 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
       }
     }
   }
+  // pairs whose band was too wide: the full traceback, per bucket, after
+  // every banded fill launch
+  if (d) {
+    for (int kind = 0; kind < kNumKinds; ++kind) {
+      if (forced != (kind == kK32)) continue;
+      if (kind == kK16Sat && !may_sat) continue;
+      for (int cls = 0; cls < kNumClasses; ++cls) {
+        if (!cls_used[cls]) continue;
+        for (int md = 0; md < kNumModes; ++md)
+          if (any_mode[md]) fp.fn[fp.n++] = K.fallback[bucket_id(kind, cls, md)];
+      }
+    }
+  }
   if (may_sat) fp.fn[fp.n++] = K.rerun[d];
   for (int i = 0; i < fp.n; ++i) {
     mica_status_t st = kernel_occupancy(device, fp.fn[i], &fp.occ[i]);
@@ -356,7 +371,9 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
 SlotShape slot_shape(const mica_batch_t* b, uint32_t flags) {
   SlotShape sh;
   const int d = (flags & (MICA_OUT_CIGAR | MICA_OUT_START)) ? 1 : 0;
-  sh.dir_bytes = d ? (size_t)(b->max_win_len + 64) * 64 * 16 : 0;
+  // the full traceback's direction words (steps x 64 lanes x 16 B), or the
+  // band records (two rows per word, 4 strips x 64 lanes), whichever is larger
+  sh.dir_bytes = d ? std::max((size_t)(b->max_win_len + 64) * 64 * 16, (size_t)(b->max_read_len / 2 + 1) * 1024) : 0;
   sh.stage_stride = b->max_read_len + b->max_win_len + 2;
   const size_t stage_bytes = d ? (size_t)8 * sh.stage_stride * 4 : 0;
   sh.slot_bytes = std::max<size_t>(align_up(sh.dir_bytes + stage_bytes, 256), 256);
@@ -532,6 +549,9 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.bucket_of = c->d_pairs;
   P.sorted = c->d_pairs + c->pair_cap;
   P.rerun = c->d_pairs + 2 * c->pair_cap;
+  P.fbsorted = c->d_pairs + 3 * c->pair_cap;
+  P.fbcount = small_fbcount(c);
+  P.fbhead = small_fbhead(c);
   P.bcount = small_bcount(c);
   P.bstart = small_bstart(c);
   P.scount = small_scount(c);
