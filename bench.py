@@ -664,6 +664,7 @@ def main():
                       "d2h_mb": round(sum(v.numel() * v.element_size() for v in out.values()) / 1e6, 1),
                       "gcups_with_transfers": round(cells / ((ms + h2d_ms + d2h_ms) * 1e-3) / 1e9, 2)},
         "saturated_pairs": int(stats["n_saturated"]),
+        "wide_band_pairs": int(stats["n_fallback"]),
         "resident_waves": int(stats["n_waves"]),
     }
     if autotune is not None:

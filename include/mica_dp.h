@@ -219,22 +219,27 @@ typedef struct {
   int32_t n_candidates;
   int32_t n_rejected;  /* candidates whose outputs differed from the default plan's */
   int32_t pad_;
-  double ms;           /* time of one call on those pairs with the chosen plan */
-  double default_ms;   /* the same with the default plan */
+  double ms;           /* time of one call on the tuning batch with the range's choice */
+  double default_ms;   /* the same before the range was tuned (its default plan) */
 } mica_tune_entry_t;
 
 /* Autotune the plan on a sample batch (same layout and flags as a batch of
- * mica_dp_align_batch; its output arrays are not written).  For every
- * 16-base read-length range (1-16, 17-32, ...) with at least 256 pairs in
- * the sample, up to 65,536 of them are aligned with each candidate plan
- * covering the range (16 lanes with the fewest rows that cover it and one
- * more row; 64 lanes with 4, 8 or 16 rows where those cover it), `reps`
- * timed calls each after one warm-up.  A candidate whose outputs (every
- * output array, every pair) differ from those of the default plan is
- * rejected; the fastest remaining one becomes the range's plan.  The
- * context's plan table is left set to the choices.  Synchronises `stream`.
- * Writes up to out_cap entries to out (may be NULL) and their number to
- * *n_out. */
+ * mica_dp_align_batch; its output arrays are not written).  The tuning batch
+ * is every sample pair of each 16-base read-length range (1-16, 17-32, ...)
+ * with at least 256 pairs in the sample, up to 65,536 pairs per range.
+ * Starting from the default plan, the ranges are tuned one at a time, the
+ * earlier choices kept: each candidate plan of the range (16 lanes with the
+ * fewest rows that cover it and one more row; 64 lanes with 4, 8 or 16 rows
+ * where those cover it) is timed on the whole tuning batch (one warm-up,
+ * then `reps` timed calls), because the plans of different ranges share
+ * the launch (the persistent kernels balance the 16-lane plans against
+ * each other, other plans run after them).  A candidate whose outputs
+ * (every output array, every pair) differ from those of the default plan is
+ * rejected; one that is more than 1% faster than the range's current choice
+ * replaces it.  The context's plan table is left set to the choices.
+ * Synchronises `stream`.  Writes up to out_cap entries to out (may be NULL;
+ * ms and default_ms are whole-batch times after and before the range was
+ * tuned) and their number to *n_out. */
 mica_status_t mica_ctx_autotune(mica_ctx_t ctx, const mica_batch_t *sample, const mica_scoring_t *scoring,
                                 uint32_t flags, void *stream, int32_t reps, mica_tune_entry_t *out,
                                 int32_t out_cap, int32_t *n_out);
@@ -253,6 +258,7 @@ typedef struct {
   int64_t n_saturated;  /* pairs re-run with 32-bit scores */
   int64_t n_waves;      /* resident waves of the persistent launch */
   int64_t scratch_bytes;
+  int64_t n_fallback;   /* pairs traced back from a full fill of direction bits (band too wide) */
 } mica_batch_stats_t;
 mica_status_t mica_ctx_last_stats(mica_ctx_t ctx, void *stream, mica_batch_stats_t *out);
 

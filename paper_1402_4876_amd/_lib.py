@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmica_dp.so")
+# MICA_LIB_PATH selects another build of the library (e.g. a variant being timed)
+LIB_PATH = os.environ.get("MICA_LIB_PATH") or os.path.join(HERE, "libmica_dp.so")
 
 OK = 0
 STATUS_NAMES = {0: "MICA_OK", -1: "MICA_ERR_INVALID_ARG", -2: "MICA_ERR_LIMIT",
@@ -73,7 +74,7 @@ class Batch(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("n_saturated", ctypes.c_int64), ("n_waves", ctypes.c_int64),
-                ("scratch_bytes", ctypes.c_int64)]
+                ("scratch_bytes", ctypes.c_int64), ("n_fallback", ctypes.c_int64)]
 
 
 class TuneEntry(ctypes.Structure):

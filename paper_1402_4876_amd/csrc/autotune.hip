@@ -24,7 +24,8 @@ namespace {
 
 constexpr int kRangeWidth = 16;       // read lengths per tuned range
 constexpr int kMinPairs = 256;        // ranges with fewer sample pairs keep their plan
-constexpr int kMaxTunePairs = 65536;  // sample pairs timed per range
+constexpr int kMaxTunePairs = 65536;  // sample pairs per range in the tuning batch
+constexpr double kMinGain = 0.01;     // a new plan must be this much faster
 
 // device buffers of one sub-batch and its outputs
 struct TuneBuffers {
@@ -168,79 +169,127 @@ mica_status_t mica_ctx_autotune(mica_ctx_t c, const mica_batch_t* sample, const 
     }
   } evg{e0, e1};
 
-  int32_t written = 0;
+  // The tuning batch: every sample pair of a tuned range, timed whole.
+  // Plans of different ranges share the launch (the persistent kernels
+  // balance the 16-lane classes against each other; other plans run as
+  // plain launches after them), so a range's candidate is judged by the
+  // time of the whole batch, one range at a time, earlier choices kept.
+  std::vector<int64_t> all;
+  std::vector<int> tuned;
   for (int r = 0; r < n_ranges; ++r) {
-    const std::vector<int64_t>& idx = members[(size_t)r];
-    if ((int64_t)idx.size() < kMinPairs) continue;
-    const int m_lo = r * kRangeWidth + 1;
-    const int m_hi = std::min((r + 1) * kRangeWidth, kMaxM);
-    const int64_t sn = (int64_t)idx.size();
-    if ((st = gather_up(tb.win_off, h_woff, idx)) != MICA_OK) return st;
-    if ((st = gather_up(tb.win_len, h_wlen, idx)) != MICA_OK) return st;
-    if ((st = gather_up(tb.read_off, h_roff, idx)) != MICA_OK) return st;
-    if ((st = gather_up(tb.read_len, h_rlen, idx)) != MICA_OK) return st;
-    if (sample->mode && (st = gather_up(tb.mode, h_mode, idx)) != MICA_OK) return st;
-    // extension start scores travel with their pairs
-    if (sample->ext_h0 && (st = gather_up(tb.ext_h0, h_h0, idx)) != MICA_OK) return st;
-    int max_w = 0;
-    for (int64_t p : idx) max_w = std::max(max_w, h_wlen[(size_t)p]);
-    mica_batch_t sb = *sample;
-    sb.win_off = tb.win_off;
-    sb.win_len = tb.win_len;
-    sb.read_off = tb.read_off;
-    sb.read_len = tb.read_len;
-    sb.mode = sample->mode ? tb.mode : nullptr;
-    sb.ext_h0 = sample->ext_h0 ? tb.ext_h0 : nullptr;
-    sb.n_pairs = sn;
-    sb.max_read_len = m_hi;
-    sb.max_win_len = max_w;
-    sb.score = tb.out;
-    sb.read_end = tb.out + sn;
-    sb.ref_end = tb.out + 2 * sn;
-    sb.read_start = tb.out + 3 * sn;
-    sb.ref_start = tb.out + 4 * sn;
-    sb.n_cigar = tb.out + 5 * sn;
-    sb.status = (uint32_t*)(tb.out + 6 * sn);
-    sb.cigar = tb.cigar;
-    sb.cigar_cap = cap;
+    if ((int64_t)members[(size_t)r].size() < kMinPairs) continue;
+    tuned.push_back(r);
+    all.insert(all.end(), members[(size_t)r].begin(), members[(size_t)r].end());
+  }
+  if (tuned.empty()) return MICA_OK;
+  const int64_t sn = (int64_t)all.size();
+  if (sn > cap_n) {
+    // buffers were sized for the largest range; grow them to the whole batch
+    TuneBuffers big;
+    HIP_TRY(hipMalloc(&big.win_off, sn * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc(&big.win_len, sn * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&big.read_off, sn * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc(&big.read_len, sn * sizeof(int32_t)));
+    if (sample->mode) HIP_TRY(hipMalloc(&big.mode, sn));
+    if (sample->ext_h0) HIP_TRY(hipMalloc(&big.ext_h0, sn * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&big.out, 7 * sn * sizeof(int32_t)));
+    if (cap > 0) HIP_TRY(hipMalloc(&big.cigar, (size_t)sn * cap * sizeof(uint32_t)));
+    std::swap(tb.win_off, big.win_off);
+    std::swap(tb.win_len, big.win_len);
+    std::swap(tb.read_off, big.read_off);
+    std::swap(tb.read_len, big.read_len);
+    std::swap(tb.mode, big.mode);
+    std::swap(tb.ext_h0, big.ext_h0);
+    std::swap(tb.out, big.out);
+    std::swap(tb.cigar, big.cigar);
+  }
+  if ((st = gather_up(tb.win_off, h_woff, all)) != MICA_OK) return st;
+  if ((st = gather_up(tb.win_len, h_wlen, all)) != MICA_OK) return st;
+  if ((st = gather_up(tb.read_off, h_roff, all)) != MICA_OK) return st;
+  if ((st = gather_up(tb.read_len, h_rlen, all)) != MICA_OK) return st;
+  if (sample->mode && (st = gather_up(tb.mode, h_mode, all)) != MICA_OK) return st;
+  // extension start scores travel with their pairs
+  if (sample->ext_h0 && (st = gather_up(tb.ext_h0, h_h0, all)) != MICA_OK) return st;
+  int max_w = 0, max_m = 0, min_m = kMaxM;
+  for (int64_t p : all) {
+    max_w = std::max(max_w, h_wlen[(size_t)p]);
+    max_m = std::max(max_m, h_rlen[(size_t)p]);
+    min_m = std::min(min_m, h_rlen[(size_t)p]);
+  }
+  mica_batch_t sb = *sample;
+  sb.win_off = tb.win_off;
+  sb.win_len = tb.win_len;
+  sb.read_off = tb.read_off;
+  sb.read_len = tb.read_len;
+  sb.mode = sample->mode ? tb.mode : nullptr;
+  sb.ext_h0 = sample->ext_h0 ? tb.ext_h0 : nullptr;
+  sb.n_pairs = sn;
+  sb.max_read_len = max_m;
+  sb.min_read_len = min_m;
+  sb.max_win_len = max_w;
+  sb.score = tb.out;
+  sb.read_end = tb.out + sn;
+  sb.ref_end = tb.out + 2 * sn;
+  sb.read_start = tb.out + 3 * sn;
+  sb.ref_start = tb.out + 4 * sn;
+  sb.n_cigar = tb.out + 5 * sn;
+  sb.status = (uint32_t*)(tb.out + 6 * sn);
+  sb.cigar = tb.cigar;
+  sb.cigar_cap = cap;
 
+  // one warm-up call, then the mean of `reps` timed calls; the outputs of the
+  // last call are left in the tuning buffers
+  auto time_batch = [&](double* per) -> mica_status_t {
+    mica_status_t e;
+    if ((e = upload_plan(c)) != MICA_OK) return e;
+    if ((e = mica_dp_align_batch(c, &sb, scoring, flags, stream)) != MICA_OK) return e;
+    HIP_TRY(hipEventRecord(e0, stream));
+    for (int k = 0; k < reps; ++k)
+      if ((e = mica_dp_align_batch(c, &sb, scoring, flags, stream)) != MICA_OK) return e;
+    HIP_TRY(hipEventRecord(e1, stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    *per = (double)ms / reps;
+    return MICA_OK;
+  };
+  auto range_lo = [](int r) { return r * kRangeWidth + 1; };
+  auto range_hi = [](int r) { return std::min((r + 1) * kRangeWidth, kMaxM); };
+  // reference outputs and time: the default plan on every tuned range
+  for (int r : tuned)
+    for (int m = range_lo(r); m <= range_hi(r); ++m) c->class_of_m[m] = (uint8_t)default_class_of(range_hi(r));
+  double cur_ms = 0;
+  if ((st = time_batch(&cur_ms)) != MICA_OK) return st;
+  HostOutputs ref;
+  if ((st = to_host(&ref.v, tb.out, 7 * sn)) != MICA_OK) return st;
+  if (cap > 0 && (st = to_host(&ref.cigar, tb.cigar, sn * cap)) != MICA_OK) return st;
+
+  int32_t written = 0;
+  for (int r : tuned) {
+    const int m_lo = range_lo(r), m_hi = range_hi(r);
     const std::vector<int> cands = candidates(m_hi);
-    HostOutputs ref;
-    int best = -1, rejected = 0;
-    double best_ms = 0, default_ms = 0;
-    for (size_t ci = 0; ci < cands.size(); ++ci) {
+    int best = cands[0], rejected = 0;
+    const double before_ms = cur_ms;
+    double best_ms = cur_ms;
+    for (size_t ci = 1; ci < cands.size(); ++ci) {
       for (int m = m_lo; m <= m_hi; ++m) c->class_of_m[m] = (uint8_t)cands[ci];
-      if ((st = upload_plan(c)) != MICA_OK) return st;
-      if ((st = mica_dp_align_batch(c, &sb, scoring, flags, stream)) != MICA_OK) return st;
-      HIP_TRY(hipEventRecord(e0, stream));
-      for (int k = 0; k < reps; ++k)
-        if ((st = mica_dp_align_batch(c, &sb, scoring, flags, stream)) != MICA_OK) return st;
-      HIP_TRY(hipEventRecord(e1, stream));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      const double per = (double)ms / reps;
+      double per = 0;
+      if ((st = time_batch(&per)) != MICA_OK) return st;
       HostOutputs got;
       if ((st = to_host(&got.v, tb.out, 7 * sn)) != MICA_OK) return st;
       if (cap > 0 && (st = to_host(&got.cigar, tb.cigar, sn * cap)) != MICA_OK) return st;
-      if (ci == 0) {
-        ref = std::move(got);
-        default_ms = per;
-        best = cands[0];
-        best_ms = per;
-        continue;
-      }
       if (!same_outputs(ref, got, sn, cap, cap > 0)) {
         ++rejected;
         continue;
       }
-      if (per < best_ms) {
+      // a candidate must beat the current choice by more than timing noise
+      if (per < best_ms * (1.0 - kMinGain)) {
         best_ms = per;
         best = cands[ci];
       }
     }
     for (int m = m_lo; m <= m_hi; ++m) c->class_of_m[m] = (uint8_t)best;
-    if ((st = upload_plan(c)) != MICA_OK) return st;
+    cur_ms = best_ms;
     if (out && written < out_cap) {
       mica_tune_entry_t& e = out[written];
       std::memset(&e, 0, sizeof(e));
@@ -248,14 +297,15 @@ mica_status_t mica_ctx_autotune(mica_ctx_t c, const mica_batch_t* sample, const 
       e.m_hi = m_hi;
       e.lanes = class_lanes(best);
       e.rows = class_rows(best);
-      e.n_pairs = (int32_t)sn;
+      e.n_pairs = (int32_t)members[(size_t)r].size();
       e.n_candidates = (int32_t)cands.size();
       e.n_rejected = rejected;
       e.ms = best_ms;
-      e.default_ms = default_ms;
+      e.default_ms = before_ms;
     }
     ++written;
   }
+  if ((st = upload_plan(c)) != MICA_OK) return st;
   *n_out = out ? std::min(written, out_cap) : 0;
   return MICA_OK;
 }

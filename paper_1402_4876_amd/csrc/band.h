@@ -144,6 +144,16 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
       }
     }
   }
+  // the band and the pair's state travel to the walk through LDS (word 3 of
+  // the pair's result), so none of the values above stays live across the
+  // refill: diagonal offset + 32768 (bits 0-15), width (16-23), band (24),
+  // wide band (25), saturated (26)
+#pragma unroll
+  for (int h = 0; h < NP; ++h)
+    if (valid[h])
+      lds[kRedOff + (bg * NP + h) * 4 + 3] = (uint32_t)(dlo[h] + 32768) | ((uint32_t)(act[h] ? W[h] : 0) << 16) |
+                                             (act[h] ? 1u << 24 : 0u) | (fb[h] ? 1u << 25 : 0u) |
+                                             (sat[h] ? 1u << 26 : 0u);
   const int rows_u = wave_max_int(rows_l);
   const int ns_u = wave_max_int(ns_l);
   const int mr_u = wave_max_int(mr_l);
@@ -352,48 +362,32 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
 
   // ---- outputs and the walk -------------------------------------------------------
   // X = 16 / NP lanes of a band group walk pair h together (see the walk of
-  // the full traceback); every lane holds the walk state.
+  // the full traceback); every lane holds the walk state.  The pair's values
+  // are read again here (global arrays, LDS results) rather than kept.
   constexpr int X = 16 / NP;
   const int h = l / X;
   const int x = l - h * X;
-  int my = 0;  // index of this lane's pair among the halves
-#pragma unroll
-  for (int k = 0; k < NP; ++k) my = (k == h) ? k : my;
-  auto pick = [&](const int* v) -> int {
-    int r = v[0];
-#pragma unroll
-    for (int k = 1; k < NP; ++k) r = my == k ? v[k] : r;
-    return r;
-  };
-  bool v_ = valid[0], s_ = sat[0], f_ = fb[0];
-  uint64_t wo_ = wo[0], ro_ = ro[0];
-#pragma unroll
-  for (int k = 1; k < NP; ++k)
-    if (my == k) {
-      v_ = valid[k];
-      s_ = sat[k];
-      f_ = fb[k];
-      wo_ = wo[k];
-      ro_ = ro[k];
-    }
-  (void)wo_;
-  (void)ro_;
-  if (v_) {
-    const int p_ = pick(pid), m_ = pick(mm), n_ = pick(nn), d0_ = pick(d0);
-    const int q = bg * NP + h;
-    if (s_) {
+  const int q = bg * NP + h;
+  if (bg_ok && q < npairs) {
+    const int p_ = (int)gpairs[q];
+    const int m_ = G(prm->read_len)[p_];
+    const int n_ = G(prm->win_len)[p_];
+    const int d0_ = EXT ? 0 : PR - m_;
+    const uint32_t w3 = red[q * 4 + 3];
+    if ((w3 >> 26) & 1u) {  // saturated: the 32-bit re-run recomputes the pair
       if (x == 0) {
         const uint32_t pos = atomicAdd(&prm->counters[kCtrRerun], 1u);
         G(prm->rerun)[pos] = (uint32_t)p_;
       }
-    } else if (f_) {
+    } else if ((w3 >> 25) & 1u) {  // band too wide: the full traceback after this launch
       if (x == 0) {
         const uint32_t pos = atomicAdd(&prm->fbcount[bucket], 1u);
         G(prm->fbsorted)[G(prm->bstart)[bucket] + pos] = (uint32_t)p_;
       }
     } else {
-      const int score = pick(scs) + d0_;
-      const int ie_ = pick(ie), je_ = pick(je), dlo_ = pick(dlo), W_ = pick(W);
+      const int score = (int)red[q * 4 + 0] + d0_;
+      const int ie_ = (int)red[q * 4 + 1], je_ = (int)red[q * 4 + 2];
+      const int dlo_ = (int)(w3 & 0xFFFFu) - 32768, W_ = (int)((w3 >> 16) & 0xFFu);
       if (x == 0) {
         G(prm->score)[p_] = score;
         G(prm->read_end)[p_] = ie_;

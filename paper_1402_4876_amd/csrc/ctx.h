@@ -41,7 +41,8 @@ constexpr size_t kScount = 5 * kNumBuckets + 8 + kNumCounters;
 constexpr size_t kSfill = kScount + kNumSubBuckets;
 constexpr size_t kFbcount = kSfill + kNumSubBuckets;
 constexpr size_t kFbhead = kFbcount + kNumBuckets;
-constexpr size_t kWords = kFbhead + kNumBuckets;
+constexpr size_t kFbqstart = kFbhead + kNumBuckets;  // kNumBuckets + 1 entries
+constexpr size_t kWords = kFbqstart + kNumBuckets + 8;
 }  // namespace small
 
 // Work-queue order of the buckets (persistent parts first, each by
@@ -55,12 +56,13 @@ mica_status_t check_batch(const mica_batch_t* b, const mica_scoring_t* s, uint32
 
 // The fill launches of a batch, in launch order, and the resident blocks per
 // CU of each (its occupancy at the library's block shape).
-constexpr int kMaxFills = 2 * kNumModes + 2 * kNumBuckets + 1;
+constexpr int kMaxFills = 4 * kNumModes + 2 * kNumBuckets + 2;
 // per-pair work lists of a batch: bucket_of | sorted | rerun | fbsorted
 constexpr int kPairLists = 4;
 struct FillPlan {
   KernelFn fn[kMaxFills];
   int occ[kMaxFills];
+  bool single[kMaxFills];  // one block of 256 threads without dynamic LDS (a scan between fills)
   int n = 0;
   int occ_max = 1;
   int mode_mask = 0;  // modes the batch holds

@@ -84,12 +84,14 @@ constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
 // counters[] slots
 // (queue heads of the persistent kernels: kCtrQueueHead + queue part)
+// (queue heads of the persistent fallback kernels: kCtrFbHead + queue part)
 enum : int {
   kCtrQueueHead = 0,
   kCtrRerun = kPersistParts,
   kCtrItems,
   kCtrRerunHead,
-  kNumCounters
+  kCtrFbHead,
+  kNumCounters = kCtrFbHead + kPersistParts
 };
 
 // per-pair status bits (same values as the public header)
@@ -168,6 +170,7 @@ struct Params {
   uint32_t* fbcount;           // [kNumBuckets] pairs whose band was too wide, per bucket
   uint32_t* fbhead;            // [kNumBuckets] next work item of each fallback launch
   uint32_t* fbsorted;          // [n_pairs] those pairs, in their bucket's range of `sorted`
+  uint32_t* fbqstart;          // [kNumBuckets + 1] first fallback item of each queue position
   uint8_t* scratch;            // n_slots * slot_bytes
   uint64_t slot_bytes;         // per resident wave: direction bits + CIGAR staging
   uint64_t dir_bytes;          // direction-bit part of a slot
@@ -185,6 +188,8 @@ struct KernelTable {
   KernelFn bucket[2][kNumBuckets];  // [with traceback][bucket]
   KernelFn fallback[kNumBuckets];   // full direction-bit traceback of wide-band pairs
   KernelFn persistent[2][kNumModes][2];  // [with traceback][mode][class part]
+  KernelFn fb_persistent[kNumModes][2];  // full traceback of the wide-band pairs, [mode][class part]
+  KernelFn fbscan;
   KernelFn rerun[2];
   KernelFn zero, plan, scan, scatter;
   KernelTable();

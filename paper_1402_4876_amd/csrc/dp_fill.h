@@ -202,7 +202,11 @@ __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, int tb
 // (measured: +4% on 10^6 seed extensions, +4-5% on the mixed-length batch,
 // against the lower budgets).
 __host__ __device__ constexpr int persist_waves(int tb, int mode, int part) {
-  return tb ? 4 : (mode == 0 ? 3 : (part == 0 ? 4 : 3));
+#if defined(MICA_PERSIST_WAVES0) && defined(MICA_PERSIST_WAVES1)
+  if (tb == 1) return part == 0 ? MICA_PERSIST_WAVES0 : MICA_PERSIST_WAVES1;
+#endif
+  return tb == 2 ? (mode == 0 ? 4 : (part == 0 ? 4 : 3))
+                 : (tb ? (part == 0 ? 4 : 3) : (mode == 0 ? 3 : (part == 0 ? 4 : 3)));
 }
 
 // Lanes of one wave exchange values through LDS: LDS operations of a wave
@@ -964,7 +968,10 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_
 // Persistent launch (one per mode and class part): every resident wave takes
 // work items from its part of the queue (buckets in descending cost order)
 // until it is empty.
-template <int TB, int MODE, int PART>
+// With FB the kernel serves the persistent buckets' wide-band pairs with
+// the full traceback instead (their own item starts, counts, lists and
+// queue heads).
+template <int TB, int MODE, int PART, bool FB = false>
 __global__ __launch_bounds__(256, persist_waves(TB, MODE, PART)) void
 k_fill_persistent(const Params* __restrict__ prm) {
   constexpr int QP = persist_queue_part(MODE, PART);
@@ -978,29 +985,31 @@ k_fill_persistent(const Params* __restrict__ prm) {
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
   const int q0 = (int)prm->persist_q[QP], q1 = (int)prm->persist_q[QP + 1];
-  const uint32_t base_item = G(prm->qstart)[q0];
-  const uint32_t total = G(prm->qstart)[q1];
+  const uint32_t* qstart = FB ? prm->fbqstart : prm->qstart;
+  const uint32_t base_item = G(qstart)[q0];
+  const uint32_t total = G(qstart)[q1];
   // waves beyond the part's item count leave at once (see k_fill_bucket)
   if ((uint32_t)slot_id >= total - base_item) return;
   for (;;) {
     uint32_t v = 0;
-    if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead + QP], 1u);
+    if (lane == 0) v = atomicAdd(&prm->counters[(FB ? kCtrFbHead : kCtrQueueHead) + QP], 1u);
     const uint32_t item = base_item + wave_uniform(v);
     if (item >= total) break;
     // queue position: last q with qstart[q] <= item
     int lo = q0, hi = q1 - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (G(prm->qstart)[mid] <= item) lo = mid;
+      if (G(qstart)[mid] <= item) lo = mid;
       else hi = mid - 1;
     }
     const int bucket = (int)G(prm->qorder)[lo];
-    const uint32_t idx = item - G(prm->qstart)[lo];
+    const uint32_t idx = item - G(qstart)[lo];
     const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
     const uint32_t first = idx * (uint32_t)ppi;
-    const uint32_t cnt = G(prm->bcount)[bucket];
+    const uint32_t cnt = G(FB ? prm->fbcount : prm->bcount)[bucket];
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    dispatch<TB, MODE, CLO, CHI>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
+    dispatch<TB, MODE, CLO, CHI>(bucket, prm, (FB ? prm->fbsorted : prm->sorted) + G(prm->bstart)[bucket] + first, np,
+                                 lds, slot);
   }
 }
 

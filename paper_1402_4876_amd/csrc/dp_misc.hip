@@ -191,6 +191,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const Params* __restrict_
   (void)n_sorted;
 }
 
+// After the banded fills: the first fallback work item of every queue
+// position of the persistent buckets (the pairs whose band was too wide).
+__global__ __launch_bounds__(kScanThreads) void k_fbscan(const Params* __restrict__ prm) {
+  __shared__ uint32_t sh[kScanThreads];
+  const int q = threadIdx.x;
+  uint32_t items = 0;
+  if (q < kNumBuckets) {
+    const int b = (int)prm->qorder[q];
+    if (persistent_bucket(b)) {
+      const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), bucket_class(b));
+      items = (prm->fbcount[b] + ppi - 1) / ppi;
+    }
+  }
+  uint32_t total;
+  const uint32_t qs = block_exclusive_scan(items, sh, &total);
+  if (q < kNumBuckets) prm->fbqstart[q] = qs;
+  if (q == 0) prm->fbqstart[kNumBuckets] = total;
+}
+
 __global__ __launch_bounds__(kPlanThreads) void k_scatter(const Params* __restrict__ prm) {
   __shared__ uint32_t cnt[kNumSubBuckets];
   __shared__ uint32_t base[kNumSubBuckets];
@@ -252,6 +271,9 @@ MICA_FB_ALL(MICA_FB_DECL)
   X(1, 0, 0) X(1, 0, 1) X(1, 1, 0) X(1, 1, 1) X(1, 2, 0) X(1, 2, 1)
 #define MICA_PERSIST_DECL(dir, mode, part) void reg_persistent_##dir##_##mode##_##part(KernelTable& t);
 MICA_PERSIST_ALL(MICA_PERSIST_DECL)
+#define MICA_PERSIST_FB_ALL(X) X(0, 0) X(0, 1) X(1, 0) X(1, 1) X(2, 0) X(2, 1)
+#define MICA_PERSIST_FB_DECL(mode, part) void reg_persistent_fb_##mode##_##part(KernelTable& t);
+MICA_PERSIST_FB_ALL(MICA_PERSIST_FB_DECL)
 
 KernelTable::KernelTable() {
 #define MICA_FILL_CALL(kind, mode, dir) reg_fill_##kind##_##mode##_##dir(*this);
@@ -260,6 +282,9 @@ KernelTable::KernelTable() {
   MICA_FB_ALL(MICA_FB_CALL)
 #define MICA_PERSIST_CALL(dir, mode, part) reg_persistent_##dir##_##mode##_##part(*this);
   MICA_PERSIST_ALL(MICA_PERSIST_CALL)
+#define MICA_PERSIST_FB_CALL(mode, part) reg_persistent_fb_##mode##_##part(*this);
+  MICA_PERSIST_FB_ALL(MICA_PERSIST_FB_CALL)
+  fbscan = &k_fbscan;
   rerun[0] = &k_rerun<false>;
   rerun[1] = &k_rerun<true>;
   zero = &k_zero;

@@ -137,6 +137,7 @@ mica_status_t mica_dp_align_batch_noalloc(const mica_batch_t* b, const mica_scor
   P.fbsorted = pairs + 3 * kMaxPairs;
   P.fbcount = sm + small::kFbcount;
   P.fbhead = sm + small::kFbhead;
+  P.fbqstart = sm + small::kFbqstart;
   P.bcount = sm + small::kBcount;
   P.bstart = sm + small::kBstart;
   P.scount = sm + small::kScount;
@@ -164,7 +165,8 @@ mica_status_t mica_dp_align_batch_noalloc(const mica_batch_t* b, const mica_scor
   HIP_TRY(launch(K.scatter, pblocks, kPlanThreads, 0, stream, dp));
   for (int i = 0; i < fp.n; ++i) {
     const int64_t blocks = std::min<int64_t>((int64_t)fp.occ[i] * ds.n_cu, slots / kWavesPerBlock);
-    HIP_TRY(launch(fp.fn[i], (unsigned)std::max<int64_t>(blocks, 1), 256, kFillShmem, stream, dp));
+    if (fp.single[i]) HIP_TRY(launch(fp.fn[i], 1, 256, 0, stream, dp));
+    else HIP_TRY(launch(fp.fn[i], (unsigned)std::max<int64_t>(blocks, 1), 256, kFillShmem, stream, dp));
   }
   return MICA_OK;
 }

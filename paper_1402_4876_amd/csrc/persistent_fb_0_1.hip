@@ -1,0 +1,7 @@
+// Persistent fallback kernel: the full traceback of the wide-band pairs of the
+// persistent buckets, semi-global, reads of 161-256 bases.
+#include "dp_fill.h"
+
+namespace mica {
+void reg_persistent_fb_0_1(KernelTable& t) { t.fb_persistent[0][1] = &k_fill_persistent<kTbFull, 0, 1, true>; }
+}  // namespace mica

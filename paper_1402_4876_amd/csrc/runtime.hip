@@ -299,6 +299,7 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
   const KernelTable& K = kernels();
   FillPlan& fp = *out;
   fp.n = 0;
+  for (int i = 0; i < kMaxFills; ++i) fp.single[i] = false;
   fp.occ_max = 1;
   const int max_m = b->max_read_len, max_n = b->max_win_len;
   const int d = (flags & (MICA_OUT_CIGAR | MICA_OUT_START)) ? 1 : 0;
@@ -320,11 +321,11 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
   for (int cls = 0; cls <= kPersistMaxClass; ++cls)
     if (cls_used[cls] && class_lanes(cls) == 16) ++n_persist_cls;
   const bool persist = !plain && !forced && n_persist_cls > 1;
+  bool part_used[2] = {false, false};
+  for (int cls = 0; cls <= kPersistMaxClass; ++cls)
+    if (cls_used[cls] && class_lanes(cls) == 16) part_used[persist_part(cls)] = true;
   if (persist) {
     // persistent parts in queue order: per mode, long reads first
-    bool part_used[2] = {false, false};
-    for (int cls = 0; cls <= kPersistMaxClass; ++cls)
-      if (cls_used[cls] && class_lanes(cls) == 16) part_used[persist_part(cls)] = true;
     for (int md = 0; md < kNumModes; ++md) {
       if (!any_mode[md]) continue;
       for (int part : {1, 0})
@@ -333,34 +334,43 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
   }
   // plain launches: every bucket in plain mode, else the buckets the
   // persistent kernels do not serve
-  for (int kind = 0; kind < kNumKinds; ++kind) {
-    if (forced != (kind == kK32)) continue;
-    if (kind == kK16Sat && !may_sat) continue;
-    for (int cls = 0; cls < kNumClasses; ++cls) {
-      if (!cls_used[cls]) continue;
-      for (int md = 0; md < kNumModes; ++md) {
-        if (!any_mode[md]) continue;
-        const int bk = bucket_id(kind, cls, md);
-        if (persist && persistent_bucket(bk)) continue;
-        fp.fn[fp.n++] = K.bucket[d][bk];
-      }
-    }
-  }
-  // pairs whose band was too wide: the full traceback, per bucket, after
-  // every banded fill launch
-  if (d) {
+  auto plain_buckets = [&](const KernelFn* table) {
     for (int kind = 0; kind < kNumKinds; ++kind) {
       if (forced != (kind == kK32)) continue;
       if (kind == kK16Sat && !may_sat) continue;
       for (int cls = 0; cls < kNumClasses; ++cls) {
         if (!cls_used[cls]) continue;
-        for (int md = 0; md < kNumModes; ++md)
-          if (any_mode[md]) fp.fn[fp.n++] = K.fallback[bucket_id(kind, cls, md)];
+        for (int md = 0; md < kNumModes; ++md) {
+          if (!any_mode[md]) continue;
+          const int bk = bucket_id(kind, cls, md);
+          if (persist && persistent_bucket(bk)) continue;
+          fp.fn[fp.n++] = table[bk];
+        }
       }
     }
+  };
+  plain_buckets(K.bucket[d]);
+  // pairs whose band was too wide: the full traceback after every banded
+  // fill, by the persistent fallback kernels (one queue over the persistent
+  // buckets) and per-bucket launches for the others
+  if (d) {
+    if (persist) {
+      fp.single[fp.n] = true;
+      fp.fn[fp.n++] = K.fbscan;
+      for (int md = 0; md < kNumModes; ++md) {
+        if (!any_mode[md]) continue;
+        for (int part : {1, 0})
+          if (part_used[part]) fp.fn[fp.n++] = K.fb_persistent[md][part];
+      }
+    }
+    plain_buckets(K.fallback);
   }
   if (may_sat) fp.fn[fp.n++] = K.rerun[d];
   for (int i = 0; i < fp.n; ++i) {
+    if (fp.single[i]) {
+      fp.occ[i] = 1;
+      continue;
+    }
     mica_status_t st = kernel_occupancy(device, fp.fn[i], &fp.occ[i]);
     if (st != MICA_OK) return st;
     fp.occ_max = std::max(fp.occ_max, fp.occ[i]);
@@ -552,6 +562,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.fbsorted = c->d_pairs + 3 * c->pair_cap;
   P.fbcount = small_fbcount(c);
   P.fbhead = small_fbhead(c);
+  P.fbqstart = c->d_small + small::kFbqstart;
   P.bcount = small_bcount(c);
   P.bstart = small_bstart(c);
   P.scount = small_scount(c);
@@ -583,7 +594,8 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
     // each fill kernel gets the blocks it keeps resident (its waves index
     // the first slots of the scratch)
     const int64_t blocks = std::min<int64_t>((int64_t)fp.occ[i] * c->n_cu, slots / kWavesPerBlock);
-    seq.push_back({fp.fn[i], (unsigned)std::max<int64_t>(blocks, 1), 256, kFillShmem, true});
+    if (fp.single[i]) seq.push_back({fp.fn[i], 1, 256, 0, true});
+    else seq.push_back({fp.fn[i], (unsigned)std::max<int64_t>(blocks, 1), 256, kFillShmem, true});
   }
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (c->timing) {
@@ -634,6 +646,10 @@ mica_status_t mica_ctx_last_stats(mica_ctx_t c, void* stream, mica_batch_stats_t
   out->n_saturated = ctr[kCtrRerun];
   out->n_waves = c->last_slots;
   out->scratch_bytes = (int64_t)c->last_scratch;
+  uint32_t fbc[kNumBuckets];
+  HIP_TRY(hipMemcpy(fbc, small_fbcount(c), sizeof(fbc), hipMemcpyDeviceToHost));
+  out->n_fallback = 0;
+  for (int b = 0; b < kNumBuckets; ++b) out->n_fallback += fbc[b];
   return MICA_OK;
 }
 
