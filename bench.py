@@ -223,106 +223,159 @@ def cpu_baseline(batch, gpu_out, want_trace, target_s=12.0):
     return base, parity
 
 
-def serving_bench(n_per_rate=2000, warmup=200, pool_size=32, slots=4, fracs=(0.3, 0.6, 0.9), fifo_baseline=True):
+def serving_bench(n_per_rate=2000, warmup=200, pool_reads=200_000, slots=4, fracs=(0.3, 0.6, 0.9),
+                  fifo_baseline=True, parity_requests=4):
     """Open-loop serving of config-4 requests: a 3 Gbp reference resident on the
-    GPU, requests of 1..10,000 reads of {100, 150, 250} bp (windows 1.5 m + 64,
-    semi-global, full outputs) arriving as a Poisson stream at 0.3 / 0.6 / 0.9
-    of the saturated request rate (measured closed-loop first), through the
-    continuous-batching server and through the FIFO baseline (one request per
-    batch, one slot).  Latency = finish - scheduled arrival, on the server."""
+    GPU; each request is a distinct range (1..10,000 reads) of a pool of planted
+    {100, 150, 250} bp reads (windows 1.5 m + 64, semi-global, full outputs);
+    arrivals are a Poisson stream replayed by the library's own submitter
+    thread.  Latency = finish - scheduled arrival, on the server.
+
+    Measured: the closed-loop capacity (lambda_max) of the continuous-batching
+    server and of the FIFO baseline (one request per batch, one slot); each
+    server at 0.3 / 0.6 / 0.9 of its own lambda_max; the batching server also
+    at the FIFO baseline's rates.  A rate at or above a server's lambda_max is
+    marked overloaded.  A few requests' outputs are kept for the parity check
+    of the CPU-baseline leg."""
     import synth
     import paper_1402_4876_amd as mica
     from paper_1402_4876_amd.pack import pack_codes
     ref_len = 3_000_000_000
     t0 = time.time()
     ref = synth.serving_reference(ref_len)
-    pool = []
-    for i in range(pool_size):
-        r = synth.serving_request(ref, ref_len, i)
-        pool.append((pack_codes(r.reads), r.read_off.astype(np.uint64), r.read_len.astype(np.int32),
-                     r.win_off.astype(np.uint64), r.win_len.astype(np.int32), int(r.cells())))
-    log("serving: reference and %d-request pool in %.1fs" % (pool_size, time.time() - t0))
+    pool = synth.serving_pool(ref, ref_len, pool_reads)
+    words = pack_codes(pool.reads)
+    ro = pool.read_off.astype(np.uint64)
+    rl = pool.read_len.astype(np.int32)
+    wo = pool.win_off.astype(np.uint64)
+    wl = pool.win_len.astype(np.int32)
+    cells = rl.astype(np.int64) * wl.astype(np.int64)
+    csum = np.concatenate([[0], np.cumsum(cells)])
+    log("serving: reference and a %d-read pool in %.1fs" % (pool_reads, time.time() - t0))
+    keep = {}
 
-    def submit(srv, rid, arrival):
-        w, ro, rl, wo, wl, _ = pool[rid % pool_size]
-        srv.submit(rid, w, ro, rl, wo, wl, arrival=arrival)
+    def run(srv, first, count, arrival, id0, keep_ids=()):
+        """Replay one schedule, forget every finished request except keep_ids
+        (fetched for the parity check); returns the wall span on the server."""
+        srv.replay(words, ro, rl, wo, wl, first, count, arrival, first_id=id0)
+        want = set(range(id0, id0 + len(first)))
+        t_first = float(np.min(arrival)) if len(arrival) else srv.now()
+        while want:
+            got = srv.poll()
+            for i in got:
+                if i in keep_ids:
+                    keep[i] = srv.fetch(i)
+                else:
+                    srv.forget(i)
+                want.discard(i)
+            if not got:
+                time.sleep(0.0005)
+        lag = srv.replay_wait()
+        return srv.now() - t_first, lag
 
-    max_n = max(len(p[2]) for p in pool)
-    fetch_buf = {k: np.empty(max_n, np.int32) for k in ("score", "read_start", "read_end", "ref_start",
-                                                         "ref_end", "n_cigar", "status")}
-    fetch_buf["cigar"] = np.empty((max_n, 64), np.uint32)
+    def closed_loop(srv, n, key, id0):
+        first, count = synth.request_schedule(len(rl), n, key)
+        now = srv.now()
+        arrival = np.full(n, now, np.float64)
+        span, _ = run(srv, first, count, arrival, id0)
+        return n / span, float((csum[first + count] - csum[first]).sum()) / span / 1e9
 
-    def drain(srv, pending, until_empty):
-        # every finished request's outputs are fetched (into reused buffers)
-        while pending:
-            for i in srv.poll():
-                srv.fetch(i, out=fetch_buf)
-                pending.discard(i)
-            if not until_empty:
-                return
-            time.sleep(0.0002)
-
-    def closed_loop(srv, n, base):
-        pending = set()
-        t = srv.now()
-        for k in range(n):
-            submit(srv, base + k, t)
-            pending.add(base + k)
-        drain(srv, pending, True)
-        return n / (srv.now() - t)
-
-    def open_loop(srv, rate, n_warm, n, base, seed):
-        arr = synth.poisson_arrivals(rate, n_warm + n, seed_key=seed)
-        pending = set()
+    def open_loop(srv, rate, key, id0, keep_ids=()):
+        n = warmup + n_per_rate
+        first, count = synth.request_schedule(len(rl), n, key)
+        arr = synth.poisson_arrivals(rate, n, seed_key=key)
         start = srv.now() + 0.01
-        for k in range(n_warm + n):
-            if k == n_warm:
-                drain(srv, pending, True)
-                srv.reset_stats()
-            ts = start + arr[k]
-            while True:
-                dt = ts - srv.now()
-                if dt <= 0:
-                    break
-                if dt > 0.0005:
-                    drain(srv, pending, False)
-                    time.sleep(min(dt - 0.0003, 0.002))
-            submit(srv, base + k, ts)
-            pending.add(base + k)
-        drain(srv, pending, True)
+        # warm-up requests first, then the measured ones on the same clock
+        run(srv, first[:warmup], count[:warmup], start + arr[:warmup], id0)
+        srv.reset_stats()
+        span, lag = run(srv, first[warmup:], count[warmup:], start + arr[warmup:], id0 + warmup, keep_ids)
         st = srv.stats()
         return {"rate_rps": round(rate, 1), "p50_ms": round(st["p50_s"] * 1e3, 3),
-                "p99_ms": round(st["p99_s"] * 1e3, 3), "gcups": round(st["gcups"], 1)}
+                "p99_ms": round(st["p99_s"] * 1e3, 3), "gcups": round(st["gcups"], 1),
+                "replay_lag_ms": round(lag * 1e3, 3)}
 
     out = {"reference_bases": ref_len, "requests_per_rate": n_per_rate, "warmup_requests": warmup,
-           "request_pool": pool_size, "mean_cells_per_request": round(float(np.mean([p[5] for p in pool])), 1)}
+           "request_pool_reads": pool_reads, "distinct_requests": True,
+           "mean_cells_per_request": round(float(cells.mean() * 5000.5), 1), "submitter": "library replay thread"}
     srv = mica.Server(ref, ref_len, slots=slots)
+    sample_ids = []
     try:
-        closed_loop(srv, 2 * pool_size, 10_000_000)
-        lam = closed_loop(srv, 8 * pool_size, 20_000_000)
+        closed_loop(srv, 100, 90, 10_000_000)
+        lam, lam_gcups = closed_loop(srv, 2000, 91, 20_000_000)
         out["lambda_max_rps"] = round(lam, 1)
+        out["gcups_at_lambda_max"] = round(lam_gcups, 1)
         out["batching"] = {"slots": slots, "rates": []}
         for i, f in enumerate(fracs):
-            r = open_loop(srv, f * lam, warmup, n_per_rate, 30_000_000 + i * 1_000_000, seed=i)
-            r["frac_of_max"] = f
+            id0 = 30_000_000 + i * 1_000_000
+            kid = set(range(id0 + warmup, id0 + warmup + parity_requests)) if i == 1 else ()
+            r = open_loop(srv, f * lam, 100 + i, id0, kid)
+            sample_ids += sorted(kid)
+            r["frac_of_own_max"] = f
+            r["overloaded"] = f >= 1.0
             out["batching"]["rates"].append(r)
             log("serving batching %.1f x max: %s" % (f, r))
-    finally:
+    except Exception:
         srv.close()
-    if not fifo_baseline:
-        return out
-    fifo = mica.Server(ref, ref_len, slots=1, fifo=True)
-    try:
-        out["fifo_baseline"] = {"slots": 1, "rates": []}
-        out["fifo_baseline"]["lambda_max_rps"] = round(closed_loop(fifo, 4 * pool_size, 40_000_000), 1)
-        for i, f in enumerate(fracs):
-            r = open_loop(fifo, f * lam, warmup, n_per_rate, 50_000_000 + i * 1_000_000, seed=i)
-            r["frac_of_max"] = f
-            out["fifo_baseline"]["rates"].append(r)
-            log("serving fifo %.1f x max: %s" % (f, r))
-    finally:
-        fifo.close()
+        raise
+    if fifo_baseline:
+        fifo = mica.Server(ref, ref_len, slots=1, fifo=True)
+        try:
+            fl, _ = closed_loop(fifo, 300, 92, 40_000_000)
+            out["fifo_baseline"] = {"slots": 1, "lambda_max_rps": round(fl, 1), "rates": []}
+            for i, f in enumerate(fracs):
+                r = open_loop(fifo, f * fl, 200 + i, 50_000_000 + i * 1_000_000)
+                r["frac_of_own_max"] = f
+                r["overloaded"] = f >= 1.0
+                out["fifo_baseline"]["rates"].append(r)
+                log("serving fifo %.1f x its max: %s" % (f, r))
+        finally:
+            fifo.close()
+        # the batching server at the FIFO baseline's own rates (loads both sustain)
+        out["batching_at_fifo_rates"] = []
+        try:
+            for i, f in enumerate(fracs):
+                rate = f * fl
+                r = open_loop(srv, rate, 300 + i, 60_000_000 + i * 1_000_000)
+                r["frac_of_own_max"] = round(rate / lam, 4)
+                r["overloaded"] = rate >= lam
+                out["batching_at_fifo_rates"].append(r)
+                log("serving batching at fifo %.1f x max: %s" % (f, r))
+        finally:
+            srv.close()
+    else:
+        srv.close()
+    # outputs of a few served requests, with their pairs, for the CPU-baseline leg
+    sample = []
+    for rid in sample_ids:
+        i = rid - 30_000_000 - 1_000_000 - warmup
+        first, count = synth.request_schedule(len(rl), warmup + n_per_rate, 101)
+        f, c = int(first[warmup + i]), int(count[warmup + i])
+        sample.append((np.arange(f, f + c), keep.get(rid)))
+    out["_parity"] = (pool, sample)
     return out
+
+
+def serving_parity(pool, sample):
+    """The served outputs of a few requests against the oracle (CPU-baseline leg)."""
+    import oracle
+    import synth
+    mism = {}
+    pairs = 0
+    for idx, got in sample:
+        if got is None:
+            mism["missing"] = mism.get("missing", 0) + 1
+            continue
+        b = synth.rebase_windows(pool.subset(idx))
+        o = oracle.align_batch(b.ref, b.win_off, b.win_len, b.reads, b.read_off, b.read_len, b.mode, trace=True,
+                               cigar_cap=64, threads=usable_cores())
+        pairs += len(idx)
+        for k in ("score", "read_start", "read_end", "ref_start", "ref_end", "n_cigar"):
+            mism[k] = mism.get(k, 0) + int((got[k] != o[k]).sum())
+        mism["status"] = mism.get("status", 0) + int(((got["status"] & ~np.uint32(1)) != o["status"]).sum())
+        ncig = np.minimum(np.abs(o["n_cigar"]), 64)
+        col = np.arange(64)[None, :] < ncig[:, None]
+        mism["cigar"] = mism.get("cigar", 0) + int((((got["cigar"] != o["cigar"]) & col).any(axis=1)).sum())
+    return {"requests": len(sample), "pairs": pairs, "mismatches": mism, "exact": all(v == 0 for v in mism.values())}
 
 
 def bwt_bench(args):
@@ -496,6 +549,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-slots", type=int, default=4, help="in-flight slots of the serving measurement")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (no batch step)")
+    ap.add_argument("--no-fifo", action="store_true", help="skip the FIFO serving baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -503,7 +557,10 @@ def main():
         return copy_calibration()
     if args.serve_only:
         res = serving_bench(n_per_rate=args.serve_requests, warmup=max(args.serve_requests // 10, 20),
-                            slots=args.serve_slots, fifo_baseline=False)
+                            slots=args.serve_slots, fifo_baseline=not args.no_fifo)
+        served = res.pop("_parity")
+        if not args.no_cpu_baseline:
+            res["parity_sample"] = serving_parity(*served)
         print(json.dumps({"serving": res}), flush=True)
         return 0
     if args.gpus == 1 and args.config == "bwt":
@@ -689,13 +746,17 @@ def main():
             gcups, lp["gcups"], res["plain_per_bucket"]["bit_exact_vs_persistent"]))
     if args.config == "c1":
         res["small_batch_latency"] = small_batch_latency(ctx)
+    served = None
     if not args.no_serving:
         res["serving"] = serving_bench(n_per_rate=args.serve_requests, warmup=max(args.serve_requests // 10, 20),
                                        slots=args.serve_slots)
+        served = res["serving"].pop("_parity")
     if not args.no_cpu_baseline:
         base, parity = cpu_baseline(batch, host, want_trace)
         res["cpu_baseline"] = base
         res["parity_sample"] = parity
+        if served is not None:
+            res["serving"]["parity_sample"] = serving_parity(*served)
     print(json.dumps(res), flush=True)
     return 0
 

@@ -289,7 +289,9 @@ enum { MICA_SERVE_FIFO = 1u << 16 };
 
 /* Create a server on `hip_device`: uploads the 2-bit reference (host words,
  * ref_len bases) once; `hbm_budget_bytes` (0 = 24 GiB) bounds the device
- * memory of reference, slots' staging and their contexts' scratch;
+ * memory of reference, slots' staging and their contexts' scratch (before
+ * each batch a slot's context may grow into what the budget leaves after
+ * the other slots' current workspaces, at least 64 MiB);
  * `max_inflight_slots` in 1..16; `flags`: mica_dp_align_batch flags
  * (MICA_OUT_CIGAR keeps 64 CIGAR runs per read) and MICA_SERVE_FIFO. */
 mica_status_t mica_server_create(int hip_device, const uint32_t *host_ref2b, uint64_t ref_len,
@@ -309,6 +311,24 @@ mica_status_t mica_server_submit(mica_server_t server, uint64_t request_id, cons
                                  const uint64_t *read_off, const int32_t *read_len, const uint64_t *win_off,
                                  const int32_t *win_len, const uint8_t *mode, int64_t n,
                                  double arrival_time_s);
+
+/* Replay a request schedule from a host thread inside the library (a load
+ * generator that keeps up with high arrival rates): request r consists of
+ * reads req_first[r] .. req_first[r] + req_count[r] - 1 of the given host
+ * arrays (laid out as for mica_server_submit), gets id first_id + r and is
+ * submitted at server time arrival_s[r] (the thread sleeps until then; the
+ * latency of a request is measured from that time).  Returns at once; the
+ * arrays must stay valid until mica_server_replay_wait returns.
+ * MICA_ERR_BUSY while another replay runs. */
+mica_status_t mica_server_replay(mica_server_t server, const uint32_t *host_reads2b, const uint64_t *read_off,
+                                 const int32_t *read_len, const uint64_t *win_off, const int32_t *win_len,
+                                 const uint8_t *mode, const int64_t *req_first, const int64_t *req_count,
+                                 const double *arrival_s, int64_t n_requests, uint64_t first_id);
+
+/* Wait until the replay has submitted every request; *lag_s (may be NULL)
+ * gets how far the latest submission ran behind its scheduled time.  A
+ * request the replay could not submit is reported here. */
+mica_status_t mica_server_replay_wait(mica_server_t server, double *lag_s);
 
 /* Ids of requests finished since the last poll (up to cap); *n_done of them. */
 mica_status_t mica_server_poll(mica_server_t server, uint64_t *done_ids, int64_t cap, int64_t *n_done);

@@ -57,6 +57,36 @@ class Server:
                                                   float(arrival)))
         self._n[int(request_id)] = n
 
+    def replay(self, reads_words, read_off, read_len, win_off, win_len, req_first, req_count, arrival,
+               first_id=0, mode=None):
+        """Start the library's replay thread: request r is reads req_first[r] ..
+        + req_count[r] of the arrays, id first_id + r, submitted at server time
+        arrival[r].  The arrays are kept alive until replay_wait()."""
+        keep = [_arr(reads_words, np.uint32), _arr(read_off, np.uint64), _arr(read_len, np.int32),
+                _arr(win_off, np.uint64), _arr(win_len, np.int32), _arr(req_first, np.int64),
+                _arr(req_count, np.int64), _arr(arrival, np.float64)]
+        mp = None
+        if mode is not None:
+            md = _arr(mode, np.uint8)
+            keep.append(md)
+            mp = md[1]
+        n = len(keep[5][0])
+        _lib.check(_lib.load().mica_server_replay(self._h, keep[0][1], keep[1][1], keep[2][1], keep[3][1], keep[4][1],
+                                                  mp, keep[5][1], keep[6][1], keep[7][1], n, int(first_id)))
+        self._replay_keep = keep
+        for r in range(n):
+            self._n[int(first_id) + r] = int(keep[6][0][r])
+
+    def replay_wait(self):
+        """Wait for the replay thread; returns how far (seconds) the latest
+        submission ran behind its scheduled time."""
+        lag = ctypes.c_double()
+        try:
+            _lib.check(_lib.load().mica_server_replay_wait(self._h, ctypes.byref(lag)))
+        finally:
+            self._replay_keep = None
+        return lag.value
+
     def poll(self, cap=4096):
         ids = np.zeros(cap, np.uint64)
         k = ctypes.c_int64()
@@ -87,6 +117,12 @@ class Server:
         if not self.out_cigar:
             del out["cigar"]
         return out
+
+    def forget(self, request_id):
+        """Drop a finished request's outputs without copying them."""
+        _lib.check(_lib.load().mica_server_fetch(self._h, int(request_id), None, None, None, None, None, None, 0,
+                                                 None, None))
+        self._n.pop(int(request_id), None)
 
     def stats(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -337,6 +337,22 @@ def serving_request(ref_words, ref_len, req_id, n_reads=None, max_reads=10_000):
                    e - win_off, None, packed=True)
 
 
+def serving_pool(ref_words, ref_len, n_reads, seed=0):
+    """A pool of planted serving reads ({100, 150, 250} bp, windows 1.5 m + 64
+    anywhere in the packed reference, config-1 errors, semi-global) from
+    which requests are cut as contiguous ranges."""
+    return serving_request(ref_words, ref_len, 1_000_000 + seed, n_reads=n_reads)
+
+
+def request_schedule(n_pool, n_req, seed_key, max_reads=10_000):
+    """Requests as distinct ranges of a read pool: sizes U{1..max_reads},
+    starts uniform over the pool.  Returns (first, count) int64 arrays."""
+    rng = rng_for(4, 3, seed_key)
+    count = rng.integers(1, max_reads + 1, n_req).astype(np.int64)
+    first = (rng.random(n_req) * (n_pool - count + 1)).astype(np.int64)
+    return first, count
+
+
 def poisson_arrivals(rate, n, seed_key=0):
     """Open-loop arrival times (seconds) of n requests at the given rate."""
     rng = rng_for(4, 2, seed_key)

@@ -122,3 +122,50 @@ def test_fifo_baseline_and_errors(served):
         assert _wait(srv, [77])[77]["score"].shape == (0,)
     finally:
         srv.close()
+
+
+def test_replayed_schedule_equals_oracle(served):
+    """Requests submitted by the library's replay thread at scheduled times
+    (ranges of one read pool) are served exactly; the replay keeps up."""
+    import paper_1402_4876_amd as mica
+    b, ref_words, reads_words, _, _, _ = served
+    first, count = synth.request_schedule(b.n_pairs, 30, 7, max_reads=300)
+    srv = mica.Server(ref_words, len(b.ref), slots=3, hbm_budget_bytes=4 << 30)
+    try:
+        t0 = srv.now() + 0.01
+        arrival = t0 + np.arange(30) * 0.002
+        srv.replay(reads_words, b.read_off.astype(np.uint64), b.read_len, b.win_off.astype(np.uint64), b.win_len,
+                   first, count, arrival, first_id=900, mode=b.mode.astype(np.uint8))
+        got = _wait(srv, list(range(900, 930)))
+        lag = srv.replay_wait()
+        assert 0 <= lag < 0.5
+        st = srv.stats()
+        assert st["p99_s"] >= st["p50_s"] > 0
+    finally:
+        srv.close()
+    for r in range(30):
+        idx = np.arange(first[r], first[r] + count[r])
+        U.assert_same(got[900 + r], U.run_oracle(b, SC, idx=idx), what="replayed request %d" % r)
+
+
+def test_tight_hbm_budget_serves_long_windows():
+    """With a budget that leaves the slots little room beyond their staging,
+    batches of long windows still run (with fewer resident waves) and are
+    exact; a budget below the fixed needs is refused."""
+    import paper_1402_4876_amd as mica
+    b = synth.tiny_random(600, 200, 3000, 17)
+    ref_words = pack_codes(b.ref)
+    reads_words = pack_codes(b.reads)
+    fixed = 3 * (26 << 20) + len(ref_words) * 4  # the slots' staging (25.3 MiB each) and the reference
+    with pytest.raises(mica.MicaError):  # less than 64 MiB of workspace per slot
+        mica.Server(ref_words, len(b.ref), slots=3, hbm_budget_bytes=fixed + (100 << 20))
+    srv = mica.Server(ref_words, len(b.ref), slots=3, hbm_budget_bytes=fixed + 3 * (80 << 20))
+    try:
+        reqs = _requests(b, [100] * 6)
+        for rid, idx in enumerate(reqs):
+            _submit(srv, b, reads_words, rid, idx)
+        got = _wait(srv, list(range(len(reqs))))
+    finally:
+        srv.close()
+    g = _concat(got, list(range(len(reqs))))
+    U.assert_same(g, U.run_oracle(b, SC, idx=np.concatenate(reqs)), what="tight budget")
