@@ -722,6 +722,7 @@ def main():
                       "gcups_with_transfers": round(cells / ((ms + h2d_ms + d2h_ms) * 1e-3) / 1e9, 2)},
         "saturated_pairs": int(stats["n_saturated"]),
         "wide_band_pairs": int(stats["n_fallback"]),
+        "deferred_band_pairs": int(stats["n_deferred"]),
         "resident_waves": int(stats["n_waves"]),
     }
     if autotune is not None:

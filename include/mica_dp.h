@@ -259,6 +259,7 @@ typedef struct {
   int64_t n_waves;      /* resident waves of the persistent launch */
   int64_t scratch_bytes;
   int64_t n_fallback;   /* pairs traced back from a full fill of direction bits (band too wide) */
+  int64_t n_deferred;   /* pairs whose band (17-64 diagonals) was refilled by a later launch */
 } mica_batch_stats_t;
 mica_status_t mica_ctx_last_stats(mica_ctx_t ctx, void *stream, mica_batch_stats_t *out);
 

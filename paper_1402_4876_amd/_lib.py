@@ -75,7 +75,8 @@ class Batch(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("n_pairs", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("n_saturated", ctypes.c_int64), ("n_waves", ctypes.c_int64),
-                ("scratch_bytes", ctypes.c_int64), ("n_fallback", ctypes.c_int64)]
+                ("scratch_bytes", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+                ("n_deferred", ctypes.c_int64)]
 
 
 class TuneEntry(ctypes.Structure):

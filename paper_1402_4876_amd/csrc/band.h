@@ -26,7 +26,11 @@
 //
 // Layout.  A band group of 16 lanes (one DPP row) holds two pairs packed in
 // 16-bit halves (one pair with 32-bit values); lane l of strip s holds
-// diagonal delta_lo + 16 s + l, up to 4 strips (64 diagonals).  Row by row:
+// diagonal delta_lo + 16 s + l, up to 4 strips (64 diagonals).  Right after
+// the fill a wave refills the bands of up to 16 diagonals (one strip); a
+// pair with a wider band gets its score and end cell written and is passed
+// on to a later launch whose items hold only such pairs, so that one wide
+// band does not make the item's other pairs pay for its extra strips.  Row by row:
 // the diagonal predecessor is in the lane, the insertion comes from the next
 // diagonal one row up (a DPP shift), and the deletion, which runs along the
 // row across lanes, is a max-plus prefix scan (max over the cells to the
@@ -66,8 +70,9 @@ struct BandLds {
 
 // The banded traceback and the outputs of one work item (all lanes of the
 // wave take part).  red[] holds the fill's result per pair; sat_h[h] whether
-// pair h of this lane's fill group saturated.
-template <class V, int P, int R, int MODE>
+// pair h of this lane's fill group saturated.  DEFER false: right after the
+// fill (bands over 16 diagonals passed on); true: the passed-on pairs.
+template <class V, int P, int R, int MODE, bool DEFER>
 __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
                                                const MICA_GLOBAL uint32_t* __restrict__ gpairs, int npairs,
                                                uint32_t* lds, uint8_t* slot, const bool* sat_h, int bucket) {
@@ -77,6 +82,7 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
   constexpr bool LOCAL = (MODE == 1);
   constexpr bool EXT = (MODE == 2);
   typedef BandLds<P, R, NP> L;
+  constexpr int NS = DEFER ? kBandMaxW / 16 : kBandInlineW / 16;  // strips of the refill
   const int lane = threadIdx.x & 63;
   const int bg = lane >> 4;
   const int l = lane & 15;
@@ -90,13 +96,13 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
   // ---- per pair: result cell and band ----------------------------------------
   int pid[NP], mm[NP], nn[NP], d0[NP], ie[NP], je[NP], scs[NP], dlo[NP], W[NP], jb[NP], h0[NP];
   uint64_t wo[NP], ro[NP];
-  bool valid[NP], act[NP], fb[NP], sat[NP];
+  bool valid[NP], act[NP], fb[NP], sat[NP], dfr[NP];
   int rows_l = 0, ns_l = 0, mr_l = 0;
 #pragma unroll
   for (int h = 0; h < NP; ++h) {
     const int q = bg * NP + h;
     valid[h] = bg_ok && q < npairs;
-    act[h] = fb[h] = sat[h] = false;
+    act[h] = fb[h] = sat[h] = dfr[h] = false;
     pid[h] = -1;
     mm[h] = nn[h] = d0[h] = ie[h] = je[h] = scs[h] = h0[h] = 0;
     dlo[h] = 0;
@@ -134,7 +140,8 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         const long hib = EXT ? (long)h0[h] + (long)sa * (mm[h] < nn[h] ? mm[h] : nn[h])
                              : (long)sa * (mm[h] < nn[h] ? mm[h] : nn[h]) - d0[h];
         fb[h] = W[h] > kBandMaxW || (NP == 2 && (hib + 16L * se + so > 32767 || 16L * se + so > 32767));
-        act[h] = !fb[h];
+        dfr[h] = !DEFER && !fb[h] && W[h] > kBandInlineW;
+        act[h] = !fb[h] && !dfr[h];
         if (act[h]) {
           rows_l = ie[h] > rows_l ? ie[h] : rows_l;
           const int ns = (W[h] + 15) >> 4;
@@ -147,13 +154,13 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
   // the band and the pair's state travel to the walk through LDS (word 3 of
   // the pair's result), so none of the values above stays live across the
   // refill: diagonal offset + 32768 (bits 0-15), width (16-23), band (24),
-  // wide band (25), saturated (26)
+  // wide band (25), saturated (26), passed on (27)
 #pragma unroll
   for (int h = 0; h < NP; ++h)
     if (valid[h])
       lds[kRedOff + (bg * NP + h) * 4 + 3] = (uint32_t)(dlo[h] + 32768) | ((uint32_t)(act[h] ? W[h] : 0) << 16) |
                                              (act[h] ? 1u << 24 : 0u) | (fb[h] ? 1u << 25 : 0u) |
-                                             (sat[h] ? 1u << 26 : 0u);
+                                             (sat[h] ? 1u << 26 : 0u) | (dfr[h] ? 1u << 27 : 0u);
   const int rows_u = wave_max_int(rows_l);
   const int ns_u = wave_max_int(ns_l);
   const int mr_u = wave_max_int(mr_l);
@@ -207,8 +214,8 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
     // row 0: H(0, j) (nothing for j < 0); the insertion candidate of the row
     // below is H - o - e there (I(0, j) is -inf); lanes past a pair's band
     // hold -inf so they never feed it
-    T Hd[4], Ic[4], msk[4];
-    uint32_t acc[4];
+    T Hd[NS], Ic[NS], msk[NS];
+    uint32_t acc[NS];
     int wofs[NP];  // LDS byte offset of column i + delta_lo + l, less i
 #pragma unroll
     for (int h = 0; h < NP; ++h) wofs[h] = h * L::kCols + dlo[h] + l - jb[h];
@@ -217,7 +224,7 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
       else return (T)v0;
     };
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < NS; ++s) {
       int hv[2] = {0, 0}, iv[2] = {0, 0};
       bool mk[2] = {false, false}, neg[2] = {false, false};
 #pragma unroll
@@ -260,7 +267,7 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         bnd = pack(bv[0], bv[1]);
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < NS; ++s) {
         if (s >= ns_u) break;
         // window selector of column i + delta_lo + 16 s + l (each half its own pair)
         uint32_t rsel;
@@ -281,7 +288,7 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         const T x = V::add(Hd[s], sc);
         // insertion from the next diagonal one row up
         T old = negv;
-        if (s + 1 < 4 && s + 1 < ns_u) old = MICA_DPP(negv, Ic[s + 1 < 4 ? s + 1 : s], kDppRor15);
+        if (s + 1 < NS && s + 1 < ns_u) old = MICA_DPP(negv, Ic[s + 1 < NS ? s + 1 : s], kDppRor15);
         const T Iv = MICA_DPP(old, Ic[s], kDppShl1);
         T Hp = V::vmax(x, Iv);
         if constexpr (LOCAL) Hp = V::vmax(Hp, floor_v);
@@ -308,7 +315,7 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         if (s > 0) g = V::vmax(g, carry);
         const T excl = MICA_DPP(carry, g, kDppShr1);
         const T Dv = V::sub(excl, og);
-        if (s + 1 < ns_u) carry = V::sub(MICA_DPP(negv, g, kDppBcast15), e16);
+        if (s + 1 < NS && s + 1 < ns_u) carry = V::sub(MICA_DPP(negv, g, kDppBcast15), e16);
         const T Hv = V::vmax(Hp, Dv);
         const T Tv = V::sub(Hv, oev);
         const T Icn = V::vmax(V::sub(Iv, ev), Tv);
@@ -334,7 +341,7 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
     auto flush = [&](int i) {  // rows i and i + 1 (1-based i odd)
       const size_t base = (size_t)((i - 1) >> 1) * (size_t)ns64 + (size_t)lane;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < NS; ++s) {
         if (s >= ns_u) break;
         rec[base + (size_t)(s * 64)] = acc[s];
         acc[s] = 0;
@@ -384,11 +391,19 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         const uint32_t pos = atomicAdd(&prm->fbcount[bucket], 1u);
         G(prm->fbsorted)[G(prm->bstart)[bucket] + pos] = (uint32_t)p_;
       }
+    } else if ((w3 >> 27) & 1u) {  // band over 16 diagonals: the score now, the refill later
+      if (x == 0) {
+        G(prm->score)[p_] = (int)red[q * 4 + 0] + d0_;
+        G(prm->read_end)[p_] = (int)red[q * 4 + 1];
+        G(prm->ref_end)[p_] = (int)red[q * 4 + 2];
+        const uint32_t pos = atomicAdd(&prm->dbcount[bucket], 1u);
+        G(prm->dbsorted)[G(prm->bstart)[bucket] + pos] = (uint32_t)p_;
+      }
     } else {
       const int score = (int)red[q * 4 + 0] + d0_;
       const int ie_ = (int)red[q * 4 + 1], je_ = (int)red[q * 4 + 2];
       const int dlo_ = (int)(w3 & 0xFFFFu) - 32768, W_ = (int)((w3 >> 16) & 0xFFu);
-      if (x == 0) {
+      if (!DEFER && x == 0) {
         G(prm->score)[p_] = score;
         G(prm->read_end)[p_] = ie_;
         G(prm->ref_end)[p_] = je_;

@@ -91,7 +91,8 @@ enum : int {
   kCtrItems,
   kCtrRerunHead,
   kCtrFbHead,
-  kNumCounters = kCtrFbHead + kPersistParts
+  kCtrDbHead = kCtrFbHead + kPersistParts,  // queue heads of the deferred band kernels
+  kNumCounters = kCtrDbHead + kPersistParts
 };
 
 // per-pair status bits (same values as the public header)
@@ -121,8 +122,11 @@ constexpr int kBandWords = kRedOff;          // band codes: [0, kRedOff)
 static_assert(kRingWords + kCandWords <= kRedOff, "fill areas below the results");
 constexpr int kWavesPerBlock = 4;
 // widest band of the banded traceback (diagonals); wider pairs are traced
-// back from a full fill of direction bits instead
+// back from a full fill of direction bits instead.  Bands up to
+// kBandInlineW diagonals are refilled right after the fill; wider ones by
+// a later launch whose work items hold only such pairs.
 constexpr int kBandMaxW = 64;
+constexpr int kBandInlineW = 16;
 
 struct Params {
   // batch (device pointers owned by the caller)
@@ -171,6 +175,10 @@ struct Params {
   uint32_t* fbhead;            // [kNumBuckets] next work item of each fallback launch
   uint32_t* fbsorted;          // [n_pairs] those pairs, in their bucket's range of `sorted`
   uint32_t* fbqstart;          // [kNumBuckets + 1] first fallback item of each queue position
+  uint32_t* dbcount;           // [kNumBuckets] pairs whose band is refilled by a deferred launch, per bucket
+  uint32_t* dbhead;            // [kNumBuckets] next work item of each deferred band launch
+  uint32_t* dbsorted;          // [n_pairs] those pairs, in their bucket's range of `sorted`
+  uint32_t* dbqstart;          // [kNumBuckets + 1] first deferred item of each queue position
   uint8_t* scratch;            // n_slots * slot_bytes
   uint64_t slot_bytes;         // per resident wave: direction bits + CIGAR staging
   uint64_t dir_bytes;          // direction-bit part of a slot
@@ -190,6 +198,9 @@ struct KernelTable {
   KernelFn persistent[2][kNumModes][2];  // [with traceback][mode][class part]
   KernelFn fb_persistent[kNumModes][2];  // full traceback of the wide-band pairs, [mode][class part]
   KernelFn fbscan;
+  KernelFn deferred[kNumBuckets];        // band refill of the pairs with 17-64 diagonals
+  KernelFn db_persistent[kNumModes][2];
+  KernelFn dbscan;
   KernelFn rerun[2];
   KernelFn zero, plan, scan, scatter;
   KernelTable();

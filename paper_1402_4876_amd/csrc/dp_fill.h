@@ -169,6 +169,8 @@ __device__ __forceinline__ int base_at(const MICA_GLOBAL uint32_t* __restrict__ 
 // do, and the extra wave hides more latency than those spills cost
 // (measured on the 10-row kernels: +1.8% semi-global, +0.8% local).
 __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, int tb) {
+  // the passed-on band refills run no fill
+  if (tb == 3) return 4;
   // the banded traceback's fill keeps no direction bits: the score-only budget
   const bool dir = tb == 2;
   const int r = class_rows(cls);
@@ -205,6 +207,7 @@ __host__ __device__ constexpr int persist_waves(int tb, int mode, int part) {
 #if defined(MICA_PERSIST_WAVES0) && defined(MICA_PERSIST_WAVES1)
   if (tb == 1) return part == 0 ? MICA_PERSIST_WAVES0 : MICA_PERSIST_WAVES1;
 #endif
+  if (tb == 3) return 4;
   return tb == 2 ? (mode == 0 ? 4 : (part == 0 ? 4 : 3))
                  : (tb ? (part == 0 ? 4 : 3) : (mode == 0 ? 3 : (part == 0 ? 4 : 3)));
 }
@@ -226,10 +229,11 @@ __device__ __forceinline__ void lds_wait() {
 namespace mica {
 
 // Traceback kinds of a fill kernel: none (score and end cell only), banded
-// (score-only fill, then the band refill and walk of band.h), or full
+// (score-only fill, then the band refill and walk of band.h), full
 // (direction bits of every cell stored during the fill; the fallback for
-// pairs whose band is too wide, and the 32-bit re-run).
-enum Traceback : int { kTbNone = 0, kTbBand = 1, kTbFull = 2 };
+// pairs whose band is too wide, and the 32-bit re-run), or the band refill
+// alone of the pairs a banded fill passed on (bands of 17-64 diagonals).
+enum Traceback : int { kTbNone = 0, kTbBand = 1, kTbFull = 2, kTbDefer = 3 };
 
 // One wave-sized work item: G = 64/P groups, each aligning kPairs pairs.
 template <class V, int P, int R, int MODE, int TB, bool SAT>
@@ -256,6 +260,25 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   const MICA_GLOBAL uint32_t* __restrict__ reads2b = G(prm->reads2b);
   const MICA_GLOBAL uint32_t* __restrict__ gpairs = G(uni(pairs));
   npairs = uni(npairs);
+
+  if constexpr (TB == kTbDefer) {
+    // the fill's results (shifted score, i*, j*) come back from the outputs
+    // the banded fill wrote; none of these pairs saturated
+    uint32_t* red = lds + kRedOff;
+    if (lane < npairs) {
+      const int p = (int)gpairs[lane];
+      const int d0_ = EXT ? 0 : PR - G(prm->read_len)[p];
+      red[lane * 4 + 0] = (uint32_t)(G(prm->score)[p] - d0_);
+      red[lane * 4 + 1] = (uint32_t)G(prm->read_end)[p];
+      red[lane * 4 + 2] = (uint32_t)G(prm->ref_end)[p];
+    }
+    lds_wait();
+    bool none[NP];
+#pragma unroll
+    for (int h = 0; h < NP; ++h) none[h] = false;
+    band_traceback<V, P, R, MODE, true>(prm, gpairs, npairs, lds, slot, none, bucket);
+    return;
+  }
 
   // ---- the pairs of this lane's group --------------------------------------
   int pid[NP], m[NP], n[NP], d0[NP], h0[NP];
@@ -667,7 +690,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   }
   lds_wait();
   if constexpr (TB == kTbBand) {
-    band_traceback<V, P, R, MODE>(prm, gpairs, npairs, lds, slot, sat_h, bucket);
+    band_traceback<V, P, R, MODE, false>(prm, gpairs, npairs, lds, slot, sat_h, bucket);
     return;
   }
   if constexpr (DIR) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -968,12 +991,16 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_
 // Persistent launch (one per mode and class part): every resident wave takes
 // work items from its part of the queue (buckets in descending cost order)
 // until it is empty.
-// With FB the kernel serves the persistent buckets' wide-band pairs with
-// the full traceback instead (their own item starts, counts, lists and
-// queue heads).
-template <int TB, int MODE, int PART, bool FB = false>
+// With SIDE the kernel serves a list of the persistent buckets' pairs that
+// the banded fills passed on (their own item starts, counts, lists and queue
+// heads): with TB full, the pairs whose band was too wide; with TB defer,
+// those with bands of 17-64 diagonals.
+template <int TB, int MODE, int PART, bool SIDE = false>
 __global__ __launch_bounds__(256, persist_waves(TB, MODE, PART)) void
 k_fill_persistent(const Params* __restrict__ prm) {
+  constexpr bool FB = SIDE && TB == kTbFull;
+  constexpr bool DB = SIDE && TB == kTbDefer;
+  static_assert(!SIDE || FB || DB, "a side list is traced back in full or refilled");
   constexpr int QP = persist_queue_part(MODE, PART);
   constexpr int CLO = PART == 0 ? 0 : kPersistSmallMax + 1;
   constexpr int CHI = PART == 0 ? kPersistSmallMax : kPersistMaxClass;
@@ -985,14 +1012,14 @@ k_fill_persistent(const Params* __restrict__ prm) {
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
   const int q0 = (int)prm->persist_q[QP], q1 = (int)prm->persist_q[QP + 1];
-  const uint32_t* qstart = FB ? prm->fbqstart : prm->qstart;
+  const uint32_t* qstart = FB ? prm->fbqstart : (DB ? prm->dbqstart : prm->qstart);
   const uint32_t base_item = G(qstart)[q0];
   const uint32_t total = G(qstart)[q1];
   // waves beyond the part's item count leave at once (see k_fill_bucket)
   if ((uint32_t)slot_id >= total - base_item) return;
   for (;;) {
     uint32_t v = 0;
-    if (lane == 0) v = atomicAdd(&prm->counters[(FB ? kCtrFbHead : kCtrQueueHead) + QP], 1u);
+    if (lane == 0) v = atomicAdd(&prm->counters[(FB ? kCtrFbHead : (DB ? kCtrDbHead : kCtrQueueHead)) + QP], 1u);
     const uint32_t item = base_item + wave_uniform(v);
     if (item >= total) break;
     // queue position: last q with qstart[q] <= item
@@ -1006,10 +1033,10 @@ k_fill_persistent(const Params* __restrict__ prm) {
     const uint32_t idx = item - G(qstart)[lo];
     const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
     const uint32_t first = idx * (uint32_t)ppi;
-    const uint32_t cnt = G(FB ? prm->fbcount : prm->bcount)[bucket];
+    const uint32_t cnt = G(FB ? prm->fbcount : (DB ? prm->dbcount : prm->bcount))[bucket];
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    dispatch<TB, MODE, CLO, CHI>(bucket, prm, (FB ? prm->fbsorted : prm->sorted) + G(prm->bstart)[bucket] + first, np,
-                                 lds, slot);
+    const uint32_t* list = FB ? prm->fbsorted : (DB ? prm->dbsorted : prm->sorted);
+    dispatch<TB, MODE, CLO, CHI>(bucket, prm, list + G(prm->bstart)[bucket] + first, np, lds, slot);
   }
 }
 
@@ -1059,6 +1086,14 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) v
                                        &prm->fbhead[bucket]);
 }
 
+// Band refill of the pairs of one bucket that the banded fill passed on.
+template <int KIND, int CLS, int MODE>
+__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbDefer)) void k_band_deferred(const Params* __restrict__ prm) {
+  constexpr int bucket = bucket_id(KIND, CLS, MODE);
+  drain_list<kTbDefer, KIND, CLS, MODE>(prm, prm->dbsorted + G(prm->bstart)[bucket], G(prm->dbcount)[bucket],
+                                        &prm->dbhead[bucket]);
+}
+
 template <int TB, int KIND, int MODE, int... CLS>
 void fill_bucket_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
   ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_bucket<TB, KIND, CLS, MODE>), ...);
@@ -1066,6 +1101,10 @@ void fill_bucket_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
 template <int KIND, int MODE, int... CLS>
 void fill_fallback_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
   ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_fallback<KIND, CLS, MODE>), ...);
+}
+template <int KIND, int MODE, int... CLS>
+void band_deferred_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
+  ((out[bucket_id(KIND, CLS, MODE)] = &k_band_deferred<KIND, CLS, MODE>), ...);
 }
 using ClassSeq = std::make_integer_sequence<int, kNumClasses>;
 

@@ -39,6 +39,8 @@ __global__ void k_zero(const Params* __restrict__ prm) {
     prm->bhead[i] = 0;
     prm->fbcount[i] = 0;
     prm->fbhead[i] = 0;
+    prm->dbcount[i] = 0;
+    prm->dbhead[i] = 0;
   }
   if (i < kNumCounters) prm->counters[i] = 0;
 }
@@ -191,23 +193,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const Params* __restrict_
   (void)n_sorted;
 }
 
-// After the banded fills: the first fallback work item of every queue
-// position of the persistent buckets (the pairs whose band was too wide).
-__global__ __launch_bounds__(kScanThreads) void k_fbscan(const Params* __restrict__ prm) {
+// After the banded fills: the first work item of every queue position of
+// the persistent buckets in a list of pairs the fills sent on (DEFERRED:
+// bands of 17-64 diagonals; else bands too wide for the refill).
+template <bool DEFERRED>
+__global__ __launch_bounds__(kScanThreads) void k_listscan(const Params* __restrict__ prm) {
   __shared__ uint32_t sh[kScanThreads];
   const int q = threadIdx.x;
+  const uint32_t* count = DEFERRED ? prm->dbcount : prm->fbcount;
+  uint32_t* qstart = DEFERRED ? prm->dbqstart : prm->fbqstart;
   uint32_t items = 0;
   if (q < kNumBuckets) {
     const int b = (int)prm->qorder[q];
     if (persistent_bucket(b)) {
       const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), bucket_class(b));
-      items = (prm->fbcount[b] + ppi - 1) / ppi;
+      items = (count[b] + ppi - 1) / ppi;
     }
   }
   uint32_t total;
   const uint32_t qs = block_exclusive_scan(items, sh, &total);
-  if (q < kNumBuckets) prm->fbqstart[q] = qs;
-  if (q == 0) prm->fbqstart[kNumBuckets] = total;
+  if (q < kNumBuckets) qstart[q] = qs;
+  if (q == 0) qstart[kNumBuckets] = total;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void k_scatter(const Params* __restrict__ prm) {
@@ -274,6 +280,10 @@ MICA_PERSIST_ALL(MICA_PERSIST_DECL)
 #define MICA_PERSIST_FB_ALL(X) X(0, 0) X(0, 1) X(1, 0) X(1, 1) X(2, 0) X(2, 1)
 #define MICA_PERSIST_FB_DECL(mode, part) void reg_persistent_fb_##mode##_##part(KernelTable& t);
 MICA_PERSIST_FB_ALL(MICA_PERSIST_FB_DECL)
+#define MICA_PERSIST_DB_DECL(mode, part) void reg_persistent_db_##mode##_##part(KernelTable& t);
+MICA_PERSIST_FB_ALL(MICA_PERSIST_DB_DECL)
+#define MICA_DB_DECL(kind, mode) void reg_band_db_##kind##_##mode(KernelTable& t);
+MICA_FB_ALL(MICA_DB_DECL)
 
 KernelTable::KernelTable() {
 #define MICA_FILL_CALL(kind, mode, dir) reg_fill_##kind##_##mode##_##dir(*this);
@@ -284,7 +294,12 @@ KernelTable::KernelTable() {
   MICA_PERSIST_ALL(MICA_PERSIST_CALL)
 #define MICA_PERSIST_FB_CALL(mode, part) reg_persistent_fb_##mode##_##part(*this);
   MICA_PERSIST_FB_ALL(MICA_PERSIST_FB_CALL)
-  fbscan = &k_fbscan;
+#define MICA_PERSIST_DB_CALL(mode, part) reg_persistent_db_##mode##_##part(*this);
+  MICA_PERSIST_FB_ALL(MICA_PERSIST_DB_CALL)
+#define MICA_DB_CALL(kind, mode) reg_band_db_##kind##_##mode(*this);
+  MICA_FB_ALL(MICA_DB_CALL)
+  fbscan = &k_listscan<false>;
+  dbscan = &k_listscan<true>;
   rerun[0] = &k_rerun<false>;
   rerun[1] = &k_rerun<true>;
   zero = &k_zero;

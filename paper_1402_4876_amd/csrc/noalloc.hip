@@ -28,7 +28,7 @@ constexpr size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 constexpr size_t kOffParams = 0;
 constexpr size_t kOffSmall = kOffParams + al256(sizeof(Params));
 constexpr size_t kOffClass = kOffSmall + al256(small::kWords * 4);
-constexpr size_t kOffPairs = kOffClass + al256(kMaxM + 1);  // bucket_of | sorted | rerun | fbsorted
+constexpr size_t kOffPairs = kOffClass + al256(kMaxM + 1);  // bucket_of | sorted | rerun | fbsorted | dbsorted
 constexpr size_t kOffSlots = kOffPairs + al256((size_t)kPairLists * kMaxPairs * 4);  // traceback slots
 static_assert(kOffSlots + (size_t(64) << 20) <= kScratchBytes, "room for the traceback slots");
 static_assert(sizeof(Params) % 4 == 0, "parameter block copied as words");
@@ -138,6 +138,10 @@ mica_status_t mica_dp_align_batch_noalloc(const mica_batch_t* b, const mica_scor
   P.fbcount = sm + small::kFbcount;
   P.fbhead = sm + small::kFbhead;
   P.fbqstart = sm + small::kFbqstart;
+  P.dbsorted = pairs + 4 * kMaxPairs;
+  P.dbcount = sm + small::kDbcount;
+  P.dbhead = sm + small::kDbhead;
+  P.dbqstart = sm + small::kDbqstart;
   P.bcount = sm + small::kBcount;
   P.bstart = sm + small::kBstart;
   P.scount = sm + small::kScount;

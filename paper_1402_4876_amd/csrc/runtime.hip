@@ -350,10 +350,21 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
     }
   };
   plain_buckets(K.bucket[d]);
-  // pairs whose band was too wide: the full traceback after every banded
-  // fill, by the persistent fallback kernels (one queue over the persistent
-  // buckets) and per-bucket launches for the others
+  // pairs with bands of 17-64 diagonals: the deferred band refill; pairs
+  // whose band was too wide: the full traceback; both after every banded
+  // fill, by persistent kernels (one queue over the persistent buckets) and
+  // per-bucket launches for the others
   if (d) {
+    if (persist) {
+      fp.single[fp.n] = true;
+      fp.fn[fp.n++] = K.dbscan;
+      for (int md = 0; md < kNumModes; ++md) {
+        if (!any_mode[md]) continue;
+        for (int part : {1, 0})
+          if (part_used[part]) fp.fn[fp.n++] = K.db_persistent[md][part];
+      }
+    }
+    plain_buckets(K.deferred);
     if (persist) {
       fp.single[fp.n] = true;
       fp.fn[fp.n++] = K.fbscan;
@@ -563,6 +574,10 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.fbcount = small_fbcount(c);
   P.fbhead = small_fbhead(c);
   P.fbqstart = c->d_small + small::kFbqstart;
+  P.dbsorted = c->d_pairs + 4 * c->pair_cap;
+  P.dbcount = c->d_small + small::kDbcount;
+  P.dbhead = c->d_small + small::kDbhead;
+  P.dbqstart = c->d_small + small::kDbqstart;
   P.bcount = small_bcount(c);
   P.bstart = small_bstart(c);
   P.scount = small_scount(c);
@@ -650,6 +665,9 @@ mica_status_t mica_ctx_last_stats(mica_ctx_t c, void* stream, mica_batch_stats_t
   HIP_TRY(hipMemcpy(fbc, small_fbcount(c), sizeof(fbc), hipMemcpyDeviceToHost));
   out->n_fallback = 0;
   for (int b = 0; b < kNumBuckets; ++b) out->n_fallback += fbc[b];
+  HIP_TRY(hipMemcpy(fbc, c->d_small + small::kDbcount, sizeof(fbc), hipMemcpyDeviceToHost));
+  out->n_deferred = 0;
+  for (int b = 0; b < kNumBuckets; ++b) out->n_deferred += fbc[b];
   return MICA_OK;
 }
 
