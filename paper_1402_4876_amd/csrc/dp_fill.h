@@ -85,8 +85,10 @@ struct V16 {
   // v_perm_b32 selector that turns the signs of two difference registers
   // (a, b) into four 0x00/0xFF bytes: b.lo, b.hi, a.lo, a.hi
   static constexpr uint32_t kSignSel = 0x0B0A0908u;
-  // 0xFFFF in each half where d < 0
-  __device__ static T negmask(T d) { return as_u(as_s(d) >> (s16x2){15, 15}); }
+  // 0xFFFF in each half where d < 0 (one v_perm_b32 on the sign bits; an
+  // arithmetic shift is folded by the compiler into per-half compares and
+  // selects of three times the length)
+  __device__ static T negmask(T d) { return __builtin_amdgcn_perm(d, d, 0x09090808u); }
   __device__ static T make2(int lo, int hi) {
     return (uint32_t)(uint16_t)clamp16(lo) | ((uint32_t)(uint16_t)clamp16(hi) << 16);
   }
@@ -412,20 +414,23 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 
   const T ev = V::splat(se);
   const T oev = V::splat(oe);
-  // T and H of the row above the first lane's top row: the top boundary
-  // (0 above the dummy rows; for an extension the anchor row h0 - (o + j*e),
-  // whose T moves down by e per step)
-  T tbound = V::splat(-oe);
+  // T and I of the row above each lane's top row.  The first lane of a group
+  // gets the top boundary: T is 0 above the dummy rows (for an extension the
+  // anchor row h0 - (o + j*e), which moves down by e per step), I is -inf.
+  // The DPP move of each step writes the other lanes only, so the first
+  // lane's boundary stays in tsh / ish without a copy per step.
+  T tsh = V::splat(-oe);
   const T negv = (T)V::kNeg;
+  T ish = negv;
   T t_last = E[R - 1];  // T of the bottom row, column 0
   T i_last = negv;
   T hdiag_next = (T)0;
   if constexpr (EXT) {
     if constexpr (NP == 2) {
-      tbound = V::make2(h0[0] - so - se - oe, h0[1] - so - se - oe);
+      tsh = V::make2(h0[0] - so - se - oe, h0[1] - so - se - oe);
       hdiag_next = V::make2(h0[0], h0[1]);
     } else {
-      tbound = (T)(h0[0] - so - se - oe);
+      tsh = (T)(h0[0] - so - se - oe);
       hdiag_next = (T)h0[0];
     }
   }
@@ -434,6 +439,9 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   const uint32_t kk16 = (uint32_t)k * 0x10001u;
 
   auto fill_ring = [&](int c0) {
+    // an empty volatile statement keeps the address arithmetic below inside
+    // the (rarely taken) branch: hoisted, it costs a few instructions per step
+    asm volatile("" : "+s"(c0));
     for (int x = k; x < kRing / 2; x += P) {
       const int c = c0 + x;
       uint32_t sel = 0;
@@ -454,8 +462,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     constexpr bool CHECK = decltype(checks)::value;
     const uint32_t rsel = rs_a;
     rs_a = rs_b;
-    T tup = (T)shift_down<P>((uint32_t)t_last, (uint32_t)tbound);
-    T iup = (T)shift_down<P>((uint32_t)i_last, (uint32_t)negv);
+    tsh = (T)shift_down<P>((uint32_t)t_last, (uint32_t)tsh);
+    ish = (T)shift_down<P>((uint32_t)i_last, (uint32_t)ish);
+    T tup = tsh;
+    T iup = ish;
     T hdiag = hdiag_next;
     hdiag_next = V::add(tup, oev);
     const int j = t - k + 1;
@@ -501,10 +511,15 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
         }
         if constexpr (TRACK) {
           if constexpr (NP == 2) {
+            // a strictly better value moves the row's best and its column
             uint32_t msk = V::negmask(V::sub(bb[r], h));
-            if constexpr (CHECK) msk &= vmask;
+            if constexpr (CHECK) {
+              msk &= vmask;
+              bb[r] = bfi(msk, h, bb[r]);
+            } else {
+              bb[r] = V::vmax(bb[r], h);
+            }
             cc[r] = bfi(msk, jj, cc[r]);
-            bb[r] = bfi(msk, h, bb[r]);
           } else {
             const bool ok = (h > bb[r]) && (!CHECK || j <= n[0]);
             bb[r] = ok ? h : bb[r];
@@ -529,8 +544,9 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
       t_last = tup;
     }
     if constexpr (EXT) {
-      if constexpr (SAT) tmin = V::vmin(tmin, tbound);
-      tbound = V::sub(tbound, ev);
+      // (the other lanes of tsh hold T values of this step, already counted)
+      if constexpr (SAT) tmin = V::vmin(tmin, tsh);
+      tsh = V::sub(tsh, ev);
     }
     if (((t + 2) & (kRing / 2 - 1)) == 0) fill_ring(t + 2);
     rs_b = ring[(t + 2 - k) & (kRing - 1)];
