@@ -63,7 +63,7 @@ def kernel_source_sha():
     """SHA-256 of every source the DP fill kernels are built from, plus the build script."""
     csrc = os.path.join(ROOT, "paper_1402_4876_amd", "csrc")
     files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
-                   if f.endswith(".h") or f.startswith(("fill_", "persistent_")) or f == "dp_misc.hip")
+                   if f.endswith(".h") or f.startswith(("fill_", "persistent_", "side_")) or f == "dp_misc.hip")
     return _sha_of(files + [os.path.join(ROOT, "paper_1402_4876_amd", "build.py")])
 
 

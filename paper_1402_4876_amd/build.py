@@ -75,7 +75,7 @@ def resource_report(sources=None):
     """
     import re
     rows = []
-    for src in sources or [f for f in SOURCES if f.startswith(("fill_", "persistent_"))]:
+    for src in sources or [f for f in SOURCES if f.startswith(("fill_", "persistent_", "side_"))]:
         cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", os.devnull,
                                  "-Rpass-analysis=kernel-resource-usage"]
         out = subprocess.run(cmd, capture_output=True, text=True).stderr

@@ -40,11 +40,10 @@ constexpr size_t kBhead = 4 * kNumBuckets + 8 + kNumCounters;
 constexpr size_t kScount = 5 * kNumBuckets + 8 + kNumCounters;
 constexpr size_t kSfill = kScount + kNumSubBuckets;
 constexpr size_t kFbcount = kSfill + kNumSubBuckets;
-constexpr size_t kFbhead = kFbcount + kNumBuckets;
-constexpr size_t kFbqstart = kFbhead + kNumBuckets;  // kNumBuckets + 1 entries
+constexpr size_t kSidehead = kFbcount + kNumBuckets;
+constexpr size_t kFbqstart = kSidehead + kNumBuckets;  // kNumBuckets + 1 entries
 constexpr size_t kDbcount = kFbqstart + kNumBuckets + 8;
-constexpr size_t kDbhead = kDbcount + kNumBuckets;
-constexpr size_t kDbqstart = kDbhead + kNumBuckets;  // kNumBuckets + 1 entries
+constexpr size_t kDbqstart = kDbcount + kNumBuckets;  // kNumBuckets + 1 entries
 constexpr size_t kWords = kDbqstart + kNumBuckets + 8;
 }  // namespace small
 
@@ -59,7 +58,7 @@ mica_status_t check_batch(const mica_batch_t* b, const mica_scoring_t* s, uint32
 
 // The fill launches of a batch, in launch order, and the resident blocks per
 // CU of each (its occupancy at the library's block shape).
-constexpr int kMaxFills = 6 * kNumModes + 3 * kNumBuckets + 3;
+constexpr int kMaxFills = 4 * kNumModes + 2 * kNumBuckets + 2;
 // per-pair work lists of a batch: bucket_of | sorted | rerun | fbsorted | dbsorted
 constexpr int kPairLists = 5;
 struct FillPlan {

@@ -84,15 +84,14 @@ constexpr uint32_t kSkip = 0xFFFFFFFFu;
 
 // counters[] slots
 // (queue heads of the persistent kernels: kCtrQueueHead + queue part)
-// (queue heads of the persistent fallback kernels: kCtrFbHead + queue part)
+// (queue heads of the persistent side-list kernels: kCtrSideHead + queue part)
 enum : int {
   kCtrQueueHead = 0,
   kCtrRerun = kPersistParts,
   kCtrItems,
   kCtrRerunHead,
-  kCtrFbHead,
-  kCtrDbHead = kCtrFbHead + kPersistParts,  // queue heads of the deferred band kernels
-  kNumCounters = kCtrDbHead + kPersistParts
+  kCtrSideHead,
+  kNumCounters = kCtrSideHead + kPersistParts
 };
 
 // per-pair status bits (same values as the public header)
@@ -171,14 +170,15 @@ struct Params {
   const uint8_t* class_of_m;   // [kMaxM + 1]
   uint32_t* counters;          // [kNumCounters]
   uint32_t* bhead;             // [kNumBuckets] next work item of each plain bucket launch
-  uint32_t* fbcount;           // [kNumBuckets] pairs whose band was too wide, per bucket
-  uint32_t* fbhead;            // [kNumBuckets] next work item of each fallback launch
-  uint32_t* fbsorted;          // [n_pairs] those pairs, in their bucket's range of `sorted`
-  uint32_t* fbqstart;          // [kNumBuckets + 1] first fallback item of each queue position
-  uint32_t* dbcount;           // [kNumBuckets] pairs whose band is refilled by a deferred launch, per bucket
-  uint32_t* dbhead;            // [kNumBuckets] next work item of each deferred band launch
-  uint32_t* dbsorted;          // [n_pairs] those pairs, in their bucket's range of `sorted`
-  uint32_t* dbqstart;          // [kNumBuckets + 1] first deferred item of each queue position
+  // The side lists of the banded fills: fb, pairs whose band was too wide
+  // (full traceback); db, pairs with bands of 17-64 diagonals (refilled later)
+  uint32_t* fbcount;           // [kNumBuckets] fb pairs per bucket
+  uint32_t* fbsorted;          // [n_pairs] fb pairs, in their bucket's range of `sorted`
+  uint32_t* fbqstart;          // [kNumBuckets + 1] first fb item of each queue position
+  uint32_t* dbcount;           // [kNumBuckets] db pairs per bucket
+  uint32_t* dbsorted;          // [n_pairs] db pairs, in their bucket's range of `sorted`
+  uint32_t* dbqstart;          // [kNumBuckets + 1] first db item of each queue position
+  uint32_t* sidehead;          // [kNumBuckets] next side-list item of each per-bucket side launch
   uint8_t* scratch;            // n_slots * slot_bytes
   uint64_t slot_bytes;         // per resident wave: direction bits + CIGAR staging
   uint64_t dir_bytes;          // direction-bit part of a slot
@@ -194,13 +194,12 @@ typedef void (*KernelFn)(const Params*);
 // Kernel entry points of the library, indexed for the host runtime.
 struct KernelTable {
   KernelFn bucket[2][kNumBuckets];  // [with traceback][bucket]
-  KernelFn fallback[kNumBuckets];   // full direction-bit traceback of wide-band pairs
   KernelFn persistent[2][kNumModes][2];  // [with traceback][mode][class part]
-  KernelFn fb_persistent[kNumModes][2];  // full traceback of the wide-band pairs, [mode][class part]
-  KernelFn fbscan;
-  KernelFn deferred[kNumBuckets];        // band refill of the pairs with 17-64 diagonals
-  KernelFn db_persistent[kNumModes][2];
-  KernelFn dbscan;
+  // the side lists after the banded fills: per bucket, and persistent over
+  // the persistent buckets ([mode][class part]), after their item scan
+  KernelFn side[kNumBuckets];
+  KernelFn side_persistent[kNumModes][2];
+  KernelFn sidescan;
   KernelFn rerun[2];
   KernelFn zero, plan, scan, scatter;
   KernelTable();

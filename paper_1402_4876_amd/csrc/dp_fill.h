@@ -171,8 +171,6 @@ __device__ __forceinline__ int base_at(const MICA_GLOBAL uint32_t* __restrict__ 
 // do, and the extra wave hides more latency than those spills cost
 // (measured on the 10-row kernels: +1.8% semi-global, +0.8% local).
 __host__ __device__ constexpr int fill_waves(int kind, int cls, int mode, int tb) {
-  // the passed-on band refills run no fill
-  if (tb == 3) return 4;
   // the banded traceback's fill keeps no direction bits: the score-only budget
   const bool dir = tb == 2;
   const int r = class_rows(cls);
@@ -209,7 +207,6 @@ __host__ __device__ constexpr int persist_waves(int tb, int mode, int part) {
 #if defined(MICA_PERSIST_WAVES0) && defined(MICA_PERSIST_WAVES1)
   if (tb == 1) return part == 0 ? MICA_PERSIST_WAVES0 : MICA_PERSIST_WAVES1;
 #endif
-  if (tb == 3) return 4;
   return tb == 2 ? (mode == 0 ? 4 : (part == 0 ? 4 : 3))
                  : (tb ? (part == 0 ? 4 : 3) : (mode == 0 ? 3 : (part == 0 ? 4 : 3)));
 }
@@ -1007,16 +1004,9 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_
 // Persistent launch (one per mode and class part): every resident wave takes
 // work items from its part of the queue (buckets in descending cost order)
 // until it is empty.
-// With SIDE the kernel serves a list of the persistent buckets' pairs that
-// the banded fills passed on (their own item starts, counts, lists and queue
-// heads): with TB full, the pairs whose band was too wide; with TB defer,
-// those with bands of 17-64 diagonals.
-template <int TB, int MODE, int PART, bool SIDE = false>
+template <int TB, int MODE, int PART>
 __global__ __launch_bounds__(256, persist_waves(TB, MODE, PART)) void
 k_fill_persistent(const Params* __restrict__ prm) {
-  constexpr bool FB = SIDE && TB == kTbFull;
-  constexpr bool DB = SIDE && TB == kTbDefer;
-  static_assert(!SIDE || FB || DB, "a side list is traced back in full or refilled");
   constexpr int QP = persist_queue_part(MODE, PART);
   constexpr int CLO = PART == 0 ? 0 : kPersistSmallMax + 1;
   constexpr int CHI = PART == 0 ? kPersistSmallMax : kPersistMaxClass;
@@ -1028,17 +1018,64 @@ k_fill_persistent(const Params* __restrict__ prm) {
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
   const int q0 = (int)prm->persist_q[QP], q1 = (int)prm->persist_q[QP + 1];
-  const uint32_t* qstart = FB ? prm->fbqstart : (DB ? prm->dbqstart : prm->qstart);
-  const uint32_t base_item = G(qstart)[q0];
-  const uint32_t total = G(qstart)[q1];
+  const uint32_t base_item = G(prm->qstart)[q0];
+  const uint32_t total = G(prm->qstart)[q1];
   // waves beyond the part's item count leave at once (see k_fill_bucket)
   if ((uint32_t)slot_id >= total - base_item) return;
   for (;;) {
     uint32_t v = 0;
-    if (lane == 0) v = atomicAdd(&prm->counters[(FB ? kCtrFbHead : (DB ? kCtrDbHead : kCtrQueueHead)) + QP], 1u);
+    if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead + QP], 1u);
     const uint32_t item = base_item + wave_uniform(v);
     if (item >= total) break;
     // queue position: last q with qstart[q] <= item
+    int lo = q0, hi = q1 - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (G(prm->qstart)[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const int bucket = (int)G(prm->qorder)[lo];
+    const uint32_t idx = item - G(prm->qstart)[lo];
+    const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
+    const uint32_t first = idx * (uint32_t)ppi;
+    const uint32_t cnt = G(prm->bcount)[bucket];
+    const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
+    dispatch<TB, MODE, CLO, CHI>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
+  }
+}
+
+// Persistent launch over the side lists of the persistent buckets (one per
+// mode and class part): one queue that holds first the items of the pairs
+// whose band was too wide (full traceback: the longest items, so they start
+// first and their latency overlaps the rest), then the items of the pairs
+// with bands of 17-64 diagonals (band refill).
+template <int MODE, int PART>
+__global__ __launch_bounds__(256, persist_waves(kTbFull, MODE, PART)) void
+k_side_persistent(const Params* __restrict__ prm) {
+  constexpr int QP = persist_queue_part(MODE, PART);
+  constexpr int CLO = PART == 0 ? 0 : kPersistSmallMax + 1;
+  constexpr int CHI = PART == 0 ? kPersistSmallMax : kPersistMaxClass;
+  extern __shared__ uint32_t smem[];
+  const int wave = uni((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int slot_id = blockIdx.x * kWavesPerBlock + wave;
+  if (slot_id >= prm->n_slots) return;
+  uint32_t* lds = smem + wave * kLdsWaveWords;
+  uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
+  const int q0 = (int)prm->persist_q[QP], q1 = (int)prm->persist_q[QP + 1];
+  const uint32_t fb0 = G(prm->fbqstart)[q0];
+  const uint32_t nfb = G(prm->fbqstart)[q1] - fb0;
+  const uint32_t db0 = G(prm->dbqstart)[q0];
+  const uint32_t total = nfb + (G(prm->dbqstart)[q1] - db0);
+  if ((uint32_t)slot_id >= total) return;
+  for (;;) {
+    uint32_t v = 0;
+    if (lane == 0) v = atomicAdd(&prm->counters[kCtrSideHead + QP], 1u);
+    const uint32_t k = wave_uniform(v);
+    if (k >= total) break;
+    const bool full = k < nfb;
+    const uint32_t* qstart = full ? prm->fbqstart : prm->dbqstart;
+    const uint32_t item = full ? fb0 + k : db0 + (k - nfb);
     int lo = q0, hi = q1 - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -1049,15 +1086,15 @@ k_fill_persistent(const Params* __restrict__ prm) {
     const uint32_t idx = item - G(qstart)[lo];
     const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
     const uint32_t first = idx * (uint32_t)ppi;
-    const uint32_t cnt = G(FB ? prm->fbcount : (DB ? prm->dbcount : prm->bcount))[bucket];
+    const uint32_t cnt = G(full ? prm->fbcount : prm->dbcount)[bucket];
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    const uint32_t* list = FB ? prm->fbsorted : (DB ? prm->dbsorted : prm->sorted);
-    dispatch<TB, MODE, CLO, CHI>(bucket, prm, list + G(prm->bstart)[bucket] + first, np, lds, slot);
+    const uint32_t* list = (full ? prm->fbsorted : prm->dbsorted) + G(prm->bstart)[bucket] + first;
+    if (full) dispatch<kTbFull, MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
+    else dispatch<kTbDefer, MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
   }
 }
 
-// Waves of a plain launch take the items of one pair list (a bucket, or the
-// bucket's pairs sent back for the full traceback) from a queue head (items
+// Waves of a plain launch take the items of one bucket from a queue head (items
 // differ in cost: window lengths and traceback paths vary).  Any number of
 // waves drains the queue, so waves beyond the item count leave at once
 // rather than contend for the head (an empty list then costs its launch only).
@@ -1093,21 +1130,39 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, TB)) void k
                                   &prm->bhead[bucket]);
 }
 
-// Full traceback of the pairs of one bucket whose band was too wide (after
-// every banded fill launch).
+// The side lists of one bucket after its banded fill: the full traceback of
+// the pairs whose band was too wide (first: the longest items), then the
+// band refill of the pairs with bands of 17-64 diagonals, from one queue.
 template <int KIND, int CLS, int MODE>
-__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) void k_fill_fallback(const Params* __restrict__ prm) {
+__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) void k_side_bucket(const Params* __restrict__ prm) {
   constexpr int bucket = bucket_id(KIND, CLS, MODE);
-  drain_list<kTbFull, KIND, CLS, MODE>(prm, prm->fbsorted + G(prm->bstart)[bucket], G(prm->fbcount)[bucket],
-                                       &prm->fbhead[bucket]);
-}
-
-// Band refill of the pairs of one bucket that the banded fill passed on.
-template <int KIND, int CLS, int MODE>
-__global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbDefer)) void k_band_deferred(const Params* __restrict__ prm) {
-  constexpr int bucket = bucket_id(KIND, CLS, MODE);
-  drain_list<kTbDefer, KIND, CLS, MODE>(prm, prm->dbsorted + G(prm->bstart)[bucket], G(prm->dbcount)[bucket],
-                                        &prm->dbhead[bucket]);
+  constexpr int ppi = pairs_per_item(KIND, CLS);
+  extern __shared__ uint32_t smem[];
+  const int wave = uni((int)(threadIdx.x >> 6));
+  const int slot_id = blockIdx.x * kWavesPerBlock + wave;
+  if (slot_id >= prm->n_slots) return;
+  uint32_t* lds = smem + wave * kLdsWaveWords;
+  uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
+  const uint32_t nfb = G(prm->fbcount)[bucket], ndb = G(prm->dbcount)[bucket];
+  const uint32_t ifb = (nfb + ppi - 1) / ppi;
+  const uint32_t items = ifb + (ndb + ppi - 1) / ppi;
+  if ((uint32_t)slot_id >= items) return;
+  const uint32_t bs = G(prm->bstart)[bucket];
+  for (;;) {
+    uint32_t v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(&prm->sidehead[bucket], 1u);
+    const uint32_t it = wave_uniform(v);
+    if (it >= items) break;
+    if (it < ifb) {
+      const uint32_t first = it * ppi;
+      const int np = (int)((nfb - first) < (uint32_t)ppi ? (nfb - first) : (uint32_t)ppi);
+      run_one<kTbFull, CLS, KIND, MODE>(prm, prm->fbsorted + bs + first, np, lds, slot, bucket);
+    } else {
+      const uint32_t first = (it - ifb) * ppi;
+      const int np = (int)((ndb - first) < (uint32_t)ppi ? (ndb - first) : (uint32_t)ppi);
+      run_one<kTbDefer, CLS, KIND, MODE>(prm, prm->dbsorted + bs + first, np, lds, slot, bucket);
+    }
+  }
 }
 
 template <int TB, int KIND, int MODE, int... CLS>
@@ -1115,12 +1170,8 @@ void fill_bucket_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
   ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_bucket<TB, KIND, CLS, MODE>), ...);
 }
 template <int KIND, int MODE, int... CLS>
-void fill_fallback_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
-  ((out[bucket_id(KIND, CLS, MODE)] = &k_fill_fallback<KIND, CLS, MODE>), ...);
-}
-template <int KIND, int MODE, int... CLS>
-void band_deferred_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
-  ((out[bucket_id(KIND, CLS, MODE)] = &k_band_deferred<KIND, CLS, MODE>), ...);
+void side_bucket_table(KernelFn* out, std::integer_sequence<int, CLS...>) {
+  ((out[bucket_id(KIND, CLS, MODE)] = &k_side_bucket<KIND, CLS, MODE>), ...);
 }
 using ClassSeq = std::make_integer_sequence<int, kNumClasses>;
 

@@ -38,9 +38,8 @@ __global__ void k_zero(const Params* __restrict__ prm) {
   if (i < kNumBuckets) {
     prm->bhead[i] = 0;
     prm->fbcount[i] = 0;
-    prm->fbhead[i] = 0;
     prm->dbcount[i] = 0;
-    prm->dbhead[i] = 0;
+    prm->sidehead[i] = 0;
   }
   if (i < kNumCounters) prm->counters[i] = 0;
 }
@@ -194,26 +193,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const Params* __restrict_
 }
 
 // After the banded fills: the first work item of every queue position of
-// the persistent buckets in a list of pairs the fills sent on (DEFERRED:
-// bands of 17-64 diagonals; else bands too wide for the refill).
-template <bool DEFERRED>
-__global__ __launch_bounds__(kScanThreads) void k_listscan(const Params* __restrict__ prm) {
+// the persistent buckets in the two side lists of the fills (fb: bands too
+// wide for the refill; db: bands of 17-64 diagonals).
+__global__ __launch_bounds__(kScanThreads) void k_sidescan(const Params* __restrict__ prm) {
   __shared__ uint32_t sh[kScanThreads];
   const int q = threadIdx.x;
-  const uint32_t* count = DEFERRED ? prm->dbcount : prm->fbcount;
-  uint32_t* qstart = DEFERRED ? prm->dbqstart : prm->fbqstart;
-  uint32_t items = 0;
-  if (q < kNumBuckets) {
-    const int b = (int)prm->qorder[q];
-    if (persistent_bucket(b)) {
-      const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), bucket_class(b));
-      items = (count[b] + ppi - 1) / ppi;
+#pragma unroll 1
+  for (int list = 0; list < 2; ++list) {
+    const uint32_t* count = list ? prm->dbcount : prm->fbcount;
+    uint32_t* qstart = list ? prm->dbqstart : prm->fbqstart;
+    uint32_t items = 0;
+    if (q < kNumBuckets) {
+      const int b = (int)prm->qorder[q];
+      if (persistent_bucket(b)) {
+        const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), bucket_class(b));
+        items = (count[b] + ppi - 1) / ppi;
+      }
     }
+    uint32_t total;
+    const uint32_t qs = block_exclusive_scan(items, sh, &total);
+    if (q < kNumBuckets) qstart[q] = qs;
+    if (q == 0) qstart[kNumBuckets] = total;
+    __syncthreads();
   }
-  uint32_t total;
-  const uint32_t qs = block_exclusive_scan(items, sh, &total);
-  if (q < kNumBuckets) qstart[q] = qs;
-  if (q == 0) qstart[kNumBuckets] = total;
 }
 
 __global__ __launch_bounds__(kPlanThreads) void k_scatter(const Params* __restrict__ prm) {
@@ -269,37 +271,28 @@ namespace mica {
   X(k32, 0, 0) X(k32, 0, 1) X(k32, 1, 0) X(k32, 1, 1) \
   X(k16, 2, 0) X(k16, 2, 1) X(k16s, 2, 0) X(k16s, 2, 1) X(k32, 2, 0) X(k32, 2, 1)
 MICA_FILL_ALL(MICA_FILL_DECL)
-#define MICA_FB_ALL(X) X(k16, 0) X(k16, 1) X(k16, 2) X(k16s, 0) X(k16s, 1) X(k16s, 2) X(k32, 0) X(k32, 1) X(k32, 2)
-#define MICA_FB_DECL(kind, mode) void reg_fill_fb_##kind##_##mode(KernelTable& t);
-MICA_FB_ALL(MICA_FB_DECL)
+#define MICA_SIDE_ALL(X) X(k16, 0) X(k16, 1) X(k16, 2) X(k16s, 0) X(k16s, 1) X(k16s, 2) X(k32, 0) X(k32, 1) X(k32, 2)
+#define MICA_SIDE_DECL(kind, mode) void reg_side_##kind##_##mode(KernelTable& t);
+MICA_SIDE_ALL(MICA_SIDE_DECL)
 #define MICA_PERSIST_ALL(X) \
   X(0, 0, 0) X(0, 0, 1) X(0, 1, 0) X(0, 1, 1) X(0, 2, 0) X(0, 2, 1) \
   X(1, 0, 0) X(1, 0, 1) X(1, 1, 0) X(1, 1, 1) X(1, 2, 0) X(1, 2, 1)
 #define MICA_PERSIST_DECL(dir, mode, part) void reg_persistent_##dir##_##mode##_##part(KernelTable& t);
 MICA_PERSIST_ALL(MICA_PERSIST_DECL)
-#define MICA_PERSIST_FB_ALL(X) X(0, 0) X(0, 1) X(1, 0) X(1, 1) X(2, 0) X(2, 1)
-#define MICA_PERSIST_FB_DECL(mode, part) void reg_persistent_fb_##mode##_##part(KernelTable& t);
-MICA_PERSIST_FB_ALL(MICA_PERSIST_FB_DECL)
-#define MICA_PERSIST_DB_DECL(mode, part) void reg_persistent_db_##mode##_##part(KernelTable& t);
-MICA_PERSIST_FB_ALL(MICA_PERSIST_DB_DECL)
-#define MICA_DB_DECL(kind, mode) void reg_band_db_##kind##_##mode(KernelTable& t);
-MICA_FB_ALL(MICA_DB_DECL)
+#define MICA_PERSIST_SIDE_ALL(X) X(0, 0) X(0, 1) X(1, 0) X(1, 1) X(2, 0) X(2, 1)
+#define MICA_PERSIST_SIDE_DECL(mode, part) void reg_persistent_side_##mode##_##part(KernelTable& t);
+MICA_PERSIST_SIDE_ALL(MICA_PERSIST_SIDE_DECL)
 
 KernelTable::KernelTable() {
 #define MICA_FILL_CALL(kind, mode, dir) reg_fill_##kind##_##mode##_##dir(*this);
   MICA_FILL_ALL(MICA_FILL_CALL)
-#define MICA_FB_CALL(kind, mode) reg_fill_fb_##kind##_##mode(*this);
-  MICA_FB_ALL(MICA_FB_CALL)
+#define MICA_SIDE_CALL(kind, mode) reg_side_##kind##_##mode(*this);
+  MICA_SIDE_ALL(MICA_SIDE_CALL)
 #define MICA_PERSIST_CALL(dir, mode, part) reg_persistent_##dir##_##mode##_##part(*this);
   MICA_PERSIST_ALL(MICA_PERSIST_CALL)
-#define MICA_PERSIST_FB_CALL(mode, part) reg_persistent_fb_##mode##_##part(*this);
-  MICA_PERSIST_FB_ALL(MICA_PERSIST_FB_CALL)
-#define MICA_PERSIST_DB_CALL(mode, part) reg_persistent_db_##mode##_##part(*this);
-  MICA_PERSIST_FB_ALL(MICA_PERSIST_DB_CALL)
-#define MICA_DB_CALL(kind, mode) reg_band_db_##kind##_##mode(*this);
-  MICA_FB_ALL(MICA_DB_CALL)
-  fbscan = &k_listscan<false>;
-  dbscan = &k_listscan<true>;
+#define MICA_PERSIST_SIDE_CALL(mode, part) reg_persistent_side_##mode##_##part(*this);
+  MICA_PERSIST_SIDE_ALL(MICA_PERSIST_SIDE_CALL)
+  sidescan = &k_sidescan;
   rerun[0] = &k_rerun<false>;
   rerun[1] = &k_rerun<true>;
   zero = &k_zero;

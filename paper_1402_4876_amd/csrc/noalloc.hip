@@ -136,11 +136,10 @@ mica_status_t mica_dp_align_batch_noalloc(const mica_batch_t* b, const mica_scor
   P.rerun = pairs + 2 * kMaxPairs;
   P.fbsorted = pairs + 3 * kMaxPairs;
   P.fbcount = sm + small::kFbcount;
-  P.fbhead = sm + small::kFbhead;
+  P.sidehead = sm + small::kSidehead;
   P.fbqstart = sm + small::kFbqstart;
   P.dbsorted = pairs + 4 * kMaxPairs;
   P.dbcount = sm + small::kDbcount;
-  P.dbhead = sm + small::kDbhead;
   P.dbqstart = sm + small::kDbqstart;
   P.bcount = sm + small::kBcount;
   P.bstart = sm + small::kBstart;

@@ -60,7 +60,7 @@ uint32_t* small_bhead(mica_ctx* c) { return c->d_small + small::kBhead; }
 uint32_t* small_scount(mica_ctx* c) { return c->d_small + small::kScount; }
 uint32_t* small_sfill(mica_ctx* c) { return c->d_small + small::kSfill; }
 uint32_t* small_fbcount(mica_ctx* c) { return c->d_small + small::kFbcount; }
-uint32_t* small_fbhead(mica_ctx* c) { return c->d_small + small::kFbhead; }
+uint32_t* small_sidehead(mica_ctx* c) { return c->d_small + small::kSidehead; }
 constexpr size_t kSmallWords = small::kWords;
 
 // cost of one work item of a bucket, for the descending work-queue order
@@ -350,31 +350,21 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
     }
   };
   plain_buckets(K.bucket[d]);
-  // pairs with bands of 17-64 diagonals: the deferred band refill; pairs
-  // whose band was too wide: the full traceback; both after every banded
-  // fill, by persistent kernels (one queue over the persistent buckets) and
-  // per-bucket launches for the others
+  // the side lists of the banded fills (pairs whose band was too wide: the
+  // full traceback; bands of 17-64 diagonals: the band refill), after every
+  // banded fill: persistent kernels over the persistent buckets (one queue
+  // per mode and class part) and one launch per other bucket
   if (d) {
     if (persist) {
       fp.single[fp.n] = true;
-      fp.fn[fp.n++] = K.dbscan;
+      fp.fn[fp.n++] = K.sidescan;
       for (int md = 0; md < kNumModes; ++md) {
         if (!any_mode[md]) continue;
         for (int part : {1, 0})
-          if (part_used[part]) fp.fn[fp.n++] = K.db_persistent[md][part];
+          if (part_used[part]) fp.fn[fp.n++] = K.side_persistent[md][part];
       }
     }
-    plain_buckets(K.deferred);
-    if (persist) {
-      fp.single[fp.n] = true;
-      fp.fn[fp.n++] = K.fbscan;
-      for (int md = 0; md < kNumModes; ++md) {
-        if (!any_mode[md]) continue;
-        for (int part : {1, 0})
-          if (part_used[part]) fp.fn[fp.n++] = K.fb_persistent[md][part];
-      }
-    }
-    plain_buckets(K.fallback);
+    plain_buckets(K.side);
   }
   if (may_sat) fp.fn[fp.n++] = K.rerun[d];
   for (int i = 0; i < fp.n; ++i) {
@@ -572,11 +562,10 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.rerun = c->d_pairs + 2 * c->pair_cap;
   P.fbsorted = c->d_pairs + 3 * c->pair_cap;
   P.fbcount = small_fbcount(c);
-  P.fbhead = small_fbhead(c);
+  P.sidehead = small_sidehead(c);
   P.fbqstart = c->d_small + small::kFbqstart;
   P.dbsorted = c->d_pairs + 4 * c->pair_cap;
   P.dbcount = c->d_small + small::kDbcount;
-  P.dbhead = c->d_small + small::kDbhead;
   P.dbqstart = c->d_small + small::kDbqstart;
   P.bcount = small_bcount(c);
   P.bstart = small_bstart(c);

@@ -1,0 +1,10 @@
+// Side lists after the banded fill of each bucket (full traceback of the
+// pairs whose band was too wide, band refill of bands of 17-64 diagonals):
+// packed 16-bit scores, local.
+#include "dp_fill.h"
+
+namespace mica {
+void reg_side_k16_1(KernelTable& t) {
+  side_bucket_table<kK16, 1>(t.side, ClassSeq{});
+}
+}  // namespace mica
