@@ -608,6 +608,9 @@ def main():
     default_mode = int(batch.mode[0]) if (uniform and n) else 0
     mode_mask = int(np.bitwise_or.reduce(1 << np.unique(batch.mode).astype(np.int64))) if n else 0
     ext_h0 = torch.as_tensor(batch.h0).cuda() if batch.h0 is not None else None
+    # the anchor scores' bound, known where the batch was made (lets a batch
+    # whose extensions fit 16-bit scores skip the saturation-checking kernels)
+    max_h0 = int(batch.h0.max()) if batch.h0 is not None and n else 0
     if mode_kind == "mixed":
         loc = batch.mode == 1
         ops = float(np.dot(batch.read_len.astype(np.int64), batch.win_len.astype(np.int64) *
@@ -646,7 +649,7 @@ def main():
                        dev["read_len"], mode=mode_arg, default_mode=default_mode, out_cigar=want_trace,
                        cigar_cap=cap, force_int32=force_i32, plain=plain, max_read_len=max_m, max_win_len=max_n,
                        ref_len=dev["ref_len"], reads_len=dev["reads_len"], out=out, mode_mask=mode_mask,
-                       ext_h0=ext_h0, ext_clip=EXT_CLIP, min_read_len=min_m)
+                       ext_h0=ext_h0, ext_clip=EXT_CLIP, min_read_len=min_m, max_ext_h0=max_h0)
 
         for _ in range(args.warmup):
             step()

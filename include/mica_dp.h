@@ -155,6 +155,13 @@ typedef struct {
    * batch of one class runs it as a plain launch.  A pair below it gets
    * MICA_ST_LEN_LIMIT. */
   int32_t min_read_len;
+  /* host-side upper bound of the extension start scores (the ext_h0
+   * entries, or ext_default_h0), 1..2^20; 0 = none given (2^20 assumed).
+   * When every extension of the batch then provably stays inside 16-bit
+   * scores, no saturation-checking kernels and no 32-bit re-run are
+   * launched for it.  An extension pair above the bound gets
+   * MICA_ST_LEN_LIMIT. */
+  int32_t max_ext_h0;
 } mica_batch_t;
 
 /* Align every pair of `batch` (Methods, DP section; readings above).

@@ -140,7 +140,7 @@ def pack_2bit(codes, stream=None):
 def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring, out_start, out_cigar,
                 cigar_cap, force_int32, plain, graph, default_mode, max_read_len, max_win_len, ref_len,
                 reads_len, out, outputs=True, ext_h0=None, ext_default_h0=0, ext_clip=0, mode_mask=0,
-                min_read_len=0):
+                min_read_len=0, max_ext_h0=0):
     ref2b = _dev(ref2b, torch.int32, "ref2b")
     reads2b = _dev(reads2b, torch.int32, "reads2b")
     win_off = _dev(win_off, torch.int64, "win_off")
@@ -206,6 +206,7 @@ def _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scor
     b.ext_clip = int(ext_clip)
     b.mode_mask = int(mode_mask)
     b.min_read_len = int(min_read_len)
+    b.max_ext_h0 = int(max_ext_h0)
     a_, b_, o_, e_ = (int(x) for x in scoring)
     sc = _lib.Scoring(a_, b_, o_, e_)
     flags = (OUT_START if out_start else 0) | (OUT_CIGAR if out_cigar else 0) | \
@@ -217,7 +218,7 @@ def align_noalloc(ref2b, win_off, win_len, reads2b, read_off, read_len, mode=Non
                   out_start=False, out_cigar=False, cigar_cap=64, force_int32=False, plain=False,
                   default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
                   reads_len=None, out=None, stream=None, ext_h0=None, ext_default_h0=0, ext_clip=0,
-                  mode_mask=0, min_read_len=0):
+                  mode_mask=0, min_read_len=0, max_ext_h0=0):
     """The allocation-free call (mica_dp_align_batch_noalloc): same arguments
     and results as align() without a context; the library's workspace is one
     fixed device array per GPU, so overlapping calls on one GPU race.  Pass
@@ -226,7 +227,7 @@ def align_noalloc(ref2b, win_off, win_len, reads2b, read_off, read_len, mode=Non
                                     out_start, out_cigar, cigar_cap, force_int32, plain, False, default_mode,
                                     max_read_len, max_win_len, ref_len, reads_len, out, ext_h0=ext_h0,
                                     ext_default_h0=ext_default_h0, ext_clip=ext_clip, mode_mask=mode_mask,
-                                    min_read_len=min_read_len)
+                                    min_read_len=min_read_len, max_ext_h0=max_ext_h0)
     _lib.check(_lib.load().mica_dp_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc), flags,
                                                        _stream_handle(stream)))
     return out
@@ -236,7 +237,7 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
           out_start=False, out_cigar=False, cigar_cap=64, force_int32=False, plain=False, graph=True,
           default_mode=MODE_SEMIGLOBAL, max_read_len=None, max_win_len=None, ref_len=None,
           reads_len=None, out=None, stream=None, ext_h0=None, ext_default_h0=0, ext_clip=0,
-          mode_mask=0, min_read_len=0):
+          mode_mask=0, min_read_len=0, max_ext_h0=0):
     """Align every (read, window) pair on the GPU; returns a dict of tensors.
 
     ref2b / reads2b: int32 tensors of 2-bit packed bases; win_off / read_off:
@@ -251,14 +252,16 @@ def align(ctx, ref2b, win_off, win_len, reads2b, read_off, read_len, mode=None, 
     ``mode_mask`` (bit per mode, 0 = all) names the modes a ``mode`` array
     may hold, so kernels of absent modes are not launched; ``min_read_len``
     (with ``max_read_len``) bounds the read lengths, so a batch of one
-    length class runs that class's own kernel.  The
+    length class runs that class's own kernel; ``max_ext_h0`` (0 = none)
+    bounds the extension start scores, so a batch whose extensions provably
+    fit 16-bit scores launches no saturation-checking kernels.  The
     call is asynchronous on ``stream``.
     """
     b, sc, flags, out = _make_batch(ref2b, win_off, win_len, reads2b, read_off, read_len, mode, scoring,
                                     out_start, out_cigar, cigar_cap, force_int32, plain, graph, default_mode,
                                     max_read_len, max_win_len, ref_len, reads_len, out, ext_h0=ext_h0,
                                     ext_default_h0=ext_default_h0, ext_clip=ext_clip, mode_mask=mode_mask,
-                                    min_read_len=min_read_len)
+                                    min_read_len=min_read_len, max_ext_h0=max_ext_h0)
     _lib.check(_lib.load().mica_dp_align_batch(ctx.handle, ctypes.byref(b), ctypes.byref(sc), flags,
                                                _stream_handle(stream)))
     return out

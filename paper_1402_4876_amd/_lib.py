@@ -68,7 +68,7 @@ class Batch(ctypes.Structure):
         ("cigar", ctypes.c_void_p), ("cigar_cap", ctypes.c_int32),
         ("n_cigar", ctypes.c_void_p), ("status", ctypes.c_void_p),
         ("ext_h0", ctypes.c_void_p), ("ext_default_h0", ctypes.c_int32), ("ext_clip", ctypes.c_int32),
-        ("mode_mask", ctypes.c_int32), ("min_read_len", ctypes.c_int32),
+        ("mode_mask", ctypes.c_int32), ("min_read_len", ctypes.c_int32), ("max_ext_h0", ctypes.c_int32),
     ]
 
 

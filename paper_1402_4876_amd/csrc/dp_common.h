@@ -154,6 +154,7 @@ struct Params {
   int32_t sa, sb, so, se;  // match, mismatch, gap open, gap extend
   const int32_t* ext_h0;   // extension start score per pair (NULL: ext_default_h0)
   int32_t ext_default_h0;
+  int32_t max_h0;          // largest extension start score accepted
   int32_t ext_clip;        // extension clipping penalty
   int32_t mode_mask;       // modes the batch may hold (bit per mode)
   uint32_t flags;

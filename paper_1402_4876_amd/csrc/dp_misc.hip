@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const Params* __restrict_
       const int h0 = md == 2 ? (prm->ext_h0 ? prm->ext_h0[p] : prm->ext_default_h0) : 0;
       uint32_t st = 0;
       if (m < prm->min_m || n < 0 || m > prm->max_m || n > prm->max_n || md < 0 || md > 2 || !((prm->mode_mask >> md) & 1) ||
-          h0 < 0 || h0 > kMaxH0)
+          h0 < 0 || h0 > prm->max_h0)
         st = kStLenLimit;
       else if (wo > prm->ref_len || (uint64_t)n > prm->ref_len - wo) st = kStWinOob;
       else if (ro > prm->reads_len || (uint64_t)m > prm->reads_len - ro) st = kStReadOob;

@@ -78,12 +78,18 @@ void default_plan(mica_ctx* c) {
   c->class_dirty = true;
 }
 
-// same bound as the device planner: can every cell stay inside int16?
-bool int16_always_safe(int max_m, int max_n, const mica_scoring_t& s, bool any_local, bool any_sg) {
-  const long hi = (long)s.match * (long)std::min(max_m, max_n);
+// same bounds as the device planner: can every cell stay inside int16?
+// (extensions: start scores up to max_h0)
+bool int16_always_safe(int max_m, int max_n, const mica_scoring_t& s, bool any_local, bool any_sg, bool any_ext,
+                       int max_h0) {
+  long hi = (long)s.match * (long)std::min(max_m, max_n);
   long lo = 0;
   if (any_sg) lo = std::min(lo, -(long)(2 * s.gap_open + (long)(max_m + 1) * s.gap_extend) - (kMaxM - 1));
   if (any_local) lo = std::min(lo, -(long)(s.gap_open + s.gap_extend) - (kMaxM - 1));
+  if (any_ext) {
+    hi = std::max(hi, (long)max_h0 + (long)s.match * (long)std::min(max_m, max_n));
+    lo = std::min(lo, -3L * s.gap_open - (long)(max_m + max_n + 1) * s.gap_extend);
+  }
   return hi <= 32767 - 8 && lo >= -32767 + 8;
 }
 
@@ -254,6 +260,8 @@ mica_status_t check_batch(const mica_batch_t* b, const mica_scoring_t* s, uint32
     return fail(MICA_ERR_LIMIT, "max_read_len / max_win_len beyond the library limits");
   if (b->min_read_len < 0 || b->min_read_len > b->max_read_len)
     return fail(MICA_ERR_INVALID_ARG, "min_read_len outside [0, max_read_len]");
+  if (b->max_ext_h0 < 0 || b->max_ext_h0 > kMaxH0)
+    return fail(MICA_ERR_INVALID_ARG, "max_ext_h0 outside 0..2^20");
   const bool want_cigar = flags & MICA_OUT_CIGAR;
   const bool want_start = want_cigar || (flags & MICA_OUT_START);
   if (b->n_pairs == 0) return MICA_OK;
@@ -308,9 +316,10 @@ mica_status_t plan_fills(int device, const uint8_t* class_of_m, const mica_batch
   fp.mode_mask = mode_mask;
   const bool any_sg = mode_mask & 1, any_local = mode_mask & 2, any_ext = mode_mask & 4;
   const bool any_mode[3] = {any_sg, any_local, any_ext};
-  // extensions start from per-pair scores the host does not read: their
-  // saturating variants are always available
-  const bool may_sat = !forced && (any_ext || !int16_always_safe(max_m, max_n, *s, any_local, any_sg));
+  // extensions start from per-pair scores the host does not read: without
+  // a bound on them their saturating variants are always available
+  const bool may_sat = !forced && ((any_ext && b->max_ext_h0 == 0) ||
+                                   !int16_always_safe(max_m, max_n, *s, any_local, any_sg, any_ext, b->max_ext_h0));
   const bool plain = flags & MICA_PLAIN_LAUNCH;
   bool cls_used[kNumClasses] = {};
   for (int m = std::max(1, b->min_read_len); m <= max_m; ++m) cls_used[class_of_m[m]] = true;
@@ -408,6 +417,7 @@ void batch_params(Params* P_, const mica_batch_t* b, const mica_scoring_t* s, ui
   P.default_mode = b->default_mode;
   P.ext_h0 = b->ext_h0;
   P.ext_default_h0 = b->ext_default_h0;
+  P.max_h0 = b->max_ext_h0 ? b->max_ext_h0 : kMaxH0;
   P.ext_clip = b->ext_clip;
   P.mode_mask = mode_mask;
   P.max_m = b->max_read_len;

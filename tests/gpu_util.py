@@ -7,7 +7,7 @@ KEYS_END = ("score", "read_end", "ref_end")
 
 def run_gpu(ctx, batch, scoring=(1, -4, 6, 1), trace=True, cap=64, force_int32=False, plain=False,
             max_read_len=None, max_win_len=None, mode="batch", h0="batch", default_h0=0, clip=0,
-            min_read_len=0):
+            min_read_len=0, max_ext_h0=0):
     import torch
     import paper_1402_4876_amd as mica
     dev = mica.to_device(batch)
@@ -27,7 +27,8 @@ def run_gpu(ctx, batch, scoring=(1, -4, 6, 1), trace=True, cap=64, force_int32=F
                      force_int32=force_int32, plain=plain, ref_len=dev["ref_len"], reads_len=dev["reads_len"],
                      max_read_len=max_read_len, max_win_len=max_win_len,
                      default_mode=int(batch.mode[0]) if mode != "batch" and batch.n_pairs else 0, out=sentinel,
-                     ext_h0=h0_dev, ext_default_h0=default_h0, ext_clip=clip, min_read_len=min_read_len)
+                     ext_h0=h0_dev, ext_default_h0=default_h0, ext_clip=clip, min_read_len=min_read_len,
+                     max_ext_h0=max_ext_h0)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in out.items()}
 

@@ -160,3 +160,8 @@ def test_noalloc_rejects_too_many_pairs_before_any_device_call():
     assert lib.mica_dp_align_batch_noalloc(ctypes.byref(b), ctypes.byref(s), 0, None) == -2
     assert b"4,194,304" in lib.mica_last_error()
     assert lib.mica_dp_align_batch_noalloc(ctypes.byref(b), ctypes.byref(s), 1 << 20, None) == -1  # flag
+    b.n_pairs = 10
+    for bad in (-1, (1 << 20) + 1):
+        b.max_ext_h0 = bad
+        assert lib.mica_dp_align_batch_noalloc(ctypes.byref(b), ctypes.byref(s), 0, None) == -1
+        assert b"max_ext_h0" in lib.mica_last_error()

@@ -100,6 +100,29 @@ def test_large_anchor_scores_saturate_and_rerun(ctx):
     U.assert_same(U.run_gpu(ctx, b, SC, clip=5, plain=True), o, what="large h0 plain")
 
 
+def test_anchor_bound_skips_saturating_kernels(ctx):
+    """With a host bound on the anchor scores that keeps every extension in
+    16-bit scores, the batch launches no saturation-checking kernels and no
+    re-run, with the same results; pairs above the bound are rejected per
+    pair.  A bound too large for that keeps the saturating path."""
+    b = synth.tiny_random(3000, 150, 190, 14, mode=2)
+    rng = np.random.default_rng(14)
+    b.h0 = rng.integers(19, 61, b.n_pairs).astype(np.int32)
+    o = U.run_oracle(b, SC, clip=5)
+    g = U.run_gpu(ctx, b, SC, clip=5, max_ext_h0=60)
+    U.assert_same(g, o, what="bounded anchors")
+    U.assert_equal_outputs(g, U.run_gpu(ctx, b, SC, clip=5), "bound vs none")
+    b.h0[::7] = 61
+    g = U.run_gpu(ctx, b, SC, clip=5, max_ext_h0=60)
+    assert (g["status"][::7] == 4).all()
+    keep = np.nonzero(b.h0 <= 60)[0]
+    U.assert_same(g, U.run_oracle(b, SC, clip=5, idx=keep), idx=keep, what="below the bound")
+    b.h0[::7] = 32700
+    g = U.run_gpu(ctx, b, SC, clip=5, max_ext_h0=32700)
+    U.assert_same(g, U.run_oracle(b, SC, clip=5), what="large bound")
+    assert ((g["status"] & 1) != 0).any()
+
+
 def test_scaled_scoring_saturates(ctx):
     """Scores x 60 on reads up to 700 bases leave int16 for long reads only."""
     b = _with_h0(synth.tiny_random(400, 700, 760, 13, mode=2), 0, 30, 13)
