@@ -55,17 +55,30 @@ __device__ __forceinline__ int wave_max_int(int v) {
 // DPP moves within a 16-lane row; lanes without a source keep `old`
 #define MICA_DPP(old, src, ctrl) \
   ((T)__builtin_amdgcn_update_dpp((int)(old), (int)(src), (ctrl), 0xF, 0xF, false))
+// the same move writing 0 to lanes without a source (no copy of an old value)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_zero(uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)src, CTRL, 0xF, 0xF, true);
+}
+// a | (p & m) in one instruction (the compiler splits it into and/or trees)
+__device__ __forceinline__ uint32_t and_or(uint32_t p, uint32_t m, uint32_t a) {
+  uint32_t d;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(d) : "v"(p), "s"(m), "v"(a));
+  return d;
+}
 constexpr int kDppShl1 = 0x101, kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
 constexpr int kDppRor15 = 0x12F, kDppBcast15 = 0x15F;  // row_ror:15, row_newbcast:15
 
 // Per band group (or per wave for the 64-lane classes): read selectors per
-// row, then the window codes of each pair.
+// row, then the window codes.  Window entry e holds, for each pair, the code
+// of column e + delta_lo (one byte per pair), so that lane l of strip s reads
+// entry i + 16 s + l at row i whatever the pair's band.
 template <int P, int R, int NP>
 struct BandLds {
   static constexpr int kGroupWords = P == 64 ? kBandWords : kBandWords / 4;
   static constexpr int kRows = P * R;
-  static constexpr int kCols = ((kGroupWords - kRows) * 4) / NP;
-  static_assert(kCols >= kRows + kBandMaxW, "window codes of the widest band fit");
+  static constexpr int kEntries = kRows + kBandMaxW;
+  static_assert(kRows * 4 + kEntries * 2 <= kGroupWords * 4, "window codes of the widest band fit");
 };
 
 // The banded traceback and the outputs of one work item (all lanes of the
@@ -94,7 +107,7 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
   const uint32_t* red = lds + kRedOff;
 
   // ---- per pair: result cell and band ----------------------------------------
-  int pid[NP], mm[NP], nn[NP], d0[NP], ie[NP], je[NP], scs[NP], dlo[NP], W[NP], jb[NP], h0[NP];
+  int pid[NP], mm[NP], nn[NP], d0[NP], ie[NP], je[NP], scs[NP], dlo[NP], W[NP], h0[NP];
   uint64_t wo[NP], ro[NP];
   bool valid[NP], act[NP], fb[NP], sat[NP], dfr[NP];
   int rows_l = 0, ns_l = 0, mr_l = 0;
@@ -107,7 +120,6 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
     mm[h] = nn[h] = d0[h] = ie[h] = je[h] = scs[h] = h0[h] = 0;
     dlo[h] = 0;
     W[h] = 1;
-    jb[h] = 1;
     wo[h] = ro[h] = 0;
     if (valid[h]) {
       const int p = (int)gpairs[q];
@@ -134,7 +146,6 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         hi = hi > je[h] ? je[h] : hi;
         dlo[h] = lo;
         W[h] = hi - lo + 1;
-        jb[h] = lo >= 0 ? lo + 1 : 1;
         // 16-bit: the scan's lane offsets (up to o + 16 e) must not reach
         // the upper clamp from values up to the pair's bound
         const long hib = EXT ? (long)h0[h] + (long)sa * (mm[h] < nn[h] ? mm[h] : nn[h])
@@ -165,9 +176,9 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
   const int ns_u = wave_max_int(ns_l);
   const int mr_u = wave_max_int(mr_l);
 
-  // ---- codes in LDS: read selector per row, window byte per column ------------
+  // ---- codes in LDS: read selector per row, window codes per band entry -------
   uint32_t* gq = lds + (P == 64 ? 0 : bg * L::kGroupWords);
-  uint8_t* gw = (uint8_t*)(gq + L::kRows);
+  uint16_t* gw = (uint16_t*)(gq + L::kRows);
   if (bg_ok && rows_u > 0) {
     for (int i0 = l; i0 < rows_u; i0 += 16) {
       uint32_t qs = 0;
@@ -176,15 +187,18 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         qs |= (act[h] && i0 < ie[h]) ? V::qcode(base_at(reads2b, ro[h] + (uint64_t)i0), h) : V::qdummy(h);
       gq[i0] = qs;
     }
+    // entry e, pair h: column e + delta_lo (codes outside the window are
+    // never used: those cells are masked or off the band)
+    const int ne = rows_u + 16 * ns_u;
+    for (int e = l; e < ne; e += 16) {
+      uint32_t w = 0;
 #pragma unroll
-    for (int h = 0; h < NP; ++h) {
-      if (!act[h]) continue;
-      const int ncols = je[h] - jb[h] + 1;
-      for (int c = l; c < ncols; c += 16) {
-        const int j = jb[h] + c;
-        const uint32_t code = j <= nn[h] ? (uint32_t)base_at(ref2b, wo[h] + (uint64_t)(j - 1)) : 0u;
-        gw[h * L::kCols + c] = (uint8_t)(NP == 2 ? 2 * code : code);
+      for (int h = 0; h < NP; ++h) {
+        const int j = e + dlo[h];
+        if (act[h] && j >= 1 && j <= nn[h])
+          w |= (uint32_t)base_at(ref2b, wo[h] + (uint64_t)(j - 1)) << (8 * h + (NP == 2 ? 1 : 0));
       }
+      gw[e] = (uint16_t)w;
     }
   }
   lds_wait();
@@ -216,9 +230,11 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
     // hold -inf so they never feed it
     T Hd[NS], Ic[NS], msk[NS];
     uint32_t acc[NS];
-    int wofs[NP];  // LDS byte offset of column i + delta_lo + l, less i
-#pragma unroll
-    for (int h = 0; h < NP; ++h) wofs[h] = h * L::kCols + dlo[h] + l - jb[h];
+    const uint16_t* gwl = gw + l;
+    // the score table's low half as a register operand of the lookup
+    uint32_t tab_lo_v;
+    asm("v_mov_b32 %0, %1" : "=v"(tab_lo_v) : "s"(tab_lo));
+    constexpr uint32_t kFlip = 0x80008000u;  // signed <-> offset binary (16-bit halves)
     auto pack = [&](int v0, int v1) -> T {
       if constexpr (NP == 2) return V::make2(v0, v1);
       else return (T)v0;
@@ -272,19 +288,11 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         // window selector of column i + delta_lo + 16 s + l (each half its own pair)
         uint32_t rsel;
         {
-          int a0 = wofs[0] + i + 16 * s;
-          if (MASKED) a0 = a0 < 0 ? 0 : a0;
-          const uint32_t b0 = gw[a0];
-          if constexpr (NP == 2) {
-            int a1 = wofs[1] + i + 16 * s;
-            if (MASKED) a1 = a1 < L::kCols ? L::kCols : a1;
-            const uint32_t b1 = gw[a1];
-            rsel = __builtin_amdgcn_perm(b1, b0, 0x04040000u);
-          } else {
-            rsel = b0 * 0x01010202u;
-          }
+          const uint32_t w = gwl[i + 16 * s];
+          if constexpr (NP == 2) rsel = __builtin_amdgcn_perm(w, w, 0x01010000u);
+          else rsel = w * 0x01010202u;
         }
-        const T sc = (T)__builtin_amdgcn_perm(tab_hi, tab_lo, qs ^ rsel);
+        const T sc = (T)__builtin_amdgcn_perm(tab_hi, tab_lo_v, qs ^ rsel);
         const T x = V::add(Hd[s], sc);
         // insertion from the next diagonal one row up
         T old = negv;
@@ -307,15 +315,36 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         }
         // deletion: exclusive max-plus prefix over the row (strip-relative
         // offsets; `carry` brings the strips to the left)
-        T g = V::add(Hp, cg);
-        g = V::vmax(g, MICA_DPP(negv, g, kDppShr1));
-        g = V::vmax(g, MICA_DPP(negv, g, kDppShr2));
-        g = V::vmax(g, MICA_DPP(negv, g, kDppShr4));
-        g = V::vmax(g, MICA_DPP(negv, g, kDppShr8));
-        if (s > 0) g = V::vmax(g, carry);
-        const T excl = MICA_DPP(carry, g, kDppShr1);
-        const T Dv = V::sub(excl, og);
-        if (s + 1 < NS && s + 1 < ns_u) carry = V::sub(MICA_DPP(negv, g, kDppBcast15), e16);
+        T Dv;
+        if constexpr (NP == 2) {
+          // in offset binary (sign bit flipped) -inf is 0, which the DPP
+          // moves write into lanes without a source: no copies of -inf
+          typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+          auto umax = [](uint32_t a, uint32_t b) -> uint32_t {
+            return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                          __builtin_bit_cast(u16x2, b)));
+          };
+          uint32_t g = (uint32_t)V::add(Hp, cg) ^ kFlip;
+          g = umax(g, dpp_zero<kDppShr1>(g));
+          g = umax(g, dpp_zero<kDppShr2>(g));
+          g = umax(g, dpp_zero<kDppShr4>(g));
+          g = umax(g, dpp_zero<kDppShr8>(g));
+          if (s > 0) g = umax(g, (uint32_t)carry);
+          uint32_t excl = dpp_zero<kDppShr1>(g);
+          if (s > 0) excl = umax(excl, (uint32_t)carry);
+          Dv = V::sub((T)(excl ^ kFlip), og);
+          if (s + 1 < NS && s + 1 < ns_u) carry = (T)((uint32_t)V::sub((T)(dpp_zero<kDppBcast15>(g) ^ kFlip), e16) ^ kFlip);
+        } else {
+          T g = V::add(Hp, cg);
+          g = V::vmax(g, MICA_DPP(negv, g, kDppShr1));
+          g = V::vmax(g, MICA_DPP(negv, g, kDppShr2));
+          g = V::vmax(g, MICA_DPP(negv, g, kDppShr4));
+          g = V::vmax(g, MICA_DPP(negv, g, kDppShr8));
+          if (s > 0) g = V::vmax(g, carry);
+          const T excl = MICA_DPP(carry, g, kDppShr1);
+          Dv = V::sub(excl, og);
+          if (s + 1 < NS && s + 1 < ns_u) carry = V::sub(MICA_DPP(negv, g, kDppBcast15), e16);
+        }
         const T Hv = V::vmax(Hp, Dv);
         const T Tv = V::sub(Hv, oev);
         const T Icn = V::vmax(V::sub(Iv, ev), Tv);
@@ -327,11 +356,11 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         constexpr uint32_t M0 = 0x01010101u << (4 * PAR), M1 = 0x02020202u << (4 * PAR),
                            M2 = 0x04040404u << (4 * PAR);
         uint32_t a = acc[s];
-        a = (p01 & M0) | a;
-        a = (p23 & M1) | a;
+        a = and_or(p01, M0, a);
+        a = and_or(p23, M1, a);
         if constexpr (LOCAL) {
           const uint32_t zr = (uint32_t)V::sub(Hv, floor1);
-          a = (__builtin_amdgcn_perm(zr, zr, V::kSignSel) & M2) | a;
+          a = and_or(__builtin_amdgcn_perm(zr, zr, V::kSignSel), M2, a);
         }
         acc[s] = a;
         Hd[s] = Hv;
