@@ -330,6 +330,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   }
   const uint32_t tab_lo = ((uint32_t)sa & 0xFFFFu) | ((uint32_t)sb << 16);
   const uint32_t tab_hi = ((uint32_t)sb & 0xFFFFu) | ((uint32_t)sb << 16);
+  // the table's low half as the lookup's register operand, set once (the
+  // compiler would otherwise copy it from a scalar register every step)
+  uint32_t tab_lo_v;
+  asm("v_mov_b32 %0, %1" : "=v"(tab_lo_v) : "s"(tab_lo));
 
   // ---- column 0 ---------------------------------------------------------------
   // per row: H, and E = the next column's deletion candidate
@@ -403,7 +407,6 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 
   uint32_t* ring = lds + g * kRing;
   uint32_t* red = lds + kRedOff;     // final (score, i*, j*) per pair
-  uint32_t* cand = lds + kRingWords;  // per-lane local candidates
   // direction words per lane and step
   constexpr int NW = R <= 8 ? 2 : 4;
   MICA_GLOBAL u32x4* dir4 = (MICA_GLOBAL u32x4*)slot;
@@ -479,7 +482,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
       }
       static_for<R>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        const T s = (T)__builtin_amdgcn_perm(tab_hi, tab_lo, Q[r] ^ rsel);
+        const T s = (T)__builtin_amdgcn_perm(tab_hi, tab_lo_v, Q[r] ^ rsel);
         const T x = V::add(hdiag, s);
         const T dn = E[r];
         const T in = V::vmax(V::sub(iup, ev), tup);
@@ -615,6 +618,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     // (extension).  An extension's lane holding row m also leaves that row's
     // best (the end-to-end candidate) in gsl.
     uint32_t* gsl = lds + kGslOff;
+    int fb[NP], fc[NP], fi[NP];
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
       int b0 = EXT ? h0[h] : -d0[h], c0 = 0, i0 = 0;
@@ -642,33 +646,33 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
           }
         }
       }
-      cand[(lane * NP + h) * 3 + 0] = (uint32_t)b0;
-      cand[(lane * NP + h) * 3 + 1] = (uint32_t)c0;
-      cand[(lane * NP + h) * 3 + 2] = (uint32_t)i0;
+      // the group's best: the largest score over its lanes, then among the
+      // lanes that hold it the smallest (j, i) (j < 2^13, i < 2^11)
+      int smax = b0;
+#pragma unroll
+      for (int d = 1; d < P; d <<= 1) {
+        const int o = __shfl_xor(smax, d, 64);
+        smax = o > smax ? o : smax;
+      }
+      int key = b0 == smax ? (c0 << 11) | i0 : 0x7FFFFFFF;
+#pragma unroll
+      for (int d = 1; d < P; d <<= 1) {
+        const int o = __shfl_xor(key, d, 64);
+        key = o < key ? o : key;
+      }
+      fb[h] = smax;
+      fc[h] = key >> 11;
+      fi[h] = key & 2047;
     }
     lds_wait();
-    int fb[NP], fc[NP], fi[NP];
     if (k == P - 1) {
 #pragma unroll
       for (int h = 0; h < NP; ++h) {
-        int b0 = EXT ? h0[h] : -d0[h], c0 = 0, i0 = 0;
-        for (int kk = 0; kk < P; ++kk) {
-          const int src = (g * P + kk) * NP + h;
-          const int bv = (int)cand[src * 3 + 0], cv = (int)cand[src * 3 + 1], iv = (int)cand[src * 3 + 2];
-          if (bv > b0 || (bv == b0 && (cv < c0 || (cv == c0 && iv < i0)))) {
-            b0 = bv;
-            c0 = cv;
-            i0 = iv;
-          }
-        }
-        fb[h] = b0;
-        fc[h] = c0;
-        fi[h] = i0;
         if constexpr (EXT) {
           // end to end when that is within the clipping penalty of the early end
           const int gv = m[h] > 0 ? (int)gsl[(g * NP + h) * 2 + 0] : h0[h];
           const int gc = m[h] > 0 ? (int)gsl[(g * NP + h) * 2 + 1] : 0;
-          if ((long)gv >= (long)b0 - (long)prm->ext_clip) {
+          if ((long)gv >= (long)fb[h] - (long)prm->ext_clip) {
             fb[h] = gv;
             fc[h] = gc;
             fi[h] = m[h];
