@@ -55,6 +55,18 @@ __host__ __device__ constexpr int sub_bin(int cls, int d0) {
 __host__ __device__ constexpr int pairs_per_item(int kind, int cls) {
   return (kind == kK32 ? 1 : 2) * (64 / class_lanes(cls));
 }
+// The class whose kernels may trace a pair of class `cls` back in full when
+// its band is too wide.  For the 16-lane classes of 8 rows or more it is the
+// 64-lane class of 4 rows (256 row slots): a fourth of the rows per lane, so
+// one such item, which runs alone at the end of a small batch, takes about
+// a third of the time, for more work per pair (the extra dummy rows).  The
+// persistent side-list kernels always use it; a per-bucket side launch uses
+// it while its list is short against the resident waves.  (The planner
+// checks the 16-bit bounds with this class's dummy rows.)
+__host__ __device__ constexpr int fallback_class(int cls) {
+  return class_lanes(cls) == 16 && class_rows(cls) >= 8 ? 17 : cls;
+}
+static_assert(class_lanes(17) == 64 && class_rows(17) == 4, "the 256-row class of 64 lanes");
 
 // The persistent kernels serve the packed 16-bit buckets of the 16-lane
 // classes (the bulk of short-read work), split in two class ranges per mode

@@ -1003,6 +1003,16 @@ __device__ __forceinline__ void dispatch(int bucket, const Params* prm, const ui
   }
 }
 
+// the full traceback of a bucket's wide-band pairs, in its fallback class
+template <int MODE, int CLS, int CHI>
+__device__ __forceinline__ void dispatch_fallback(int bucket, const Params* prm, const uint32_t* pairs, int np,
+                                                  uint32_t* lds, uint8_t* slot) {
+  if constexpr (CLS <= CHI) {
+    if (bucket_class(bucket) == CLS) run_one<kTbFull, fallback_class(CLS), kK16, MODE>(prm, pairs, np, lds, slot, bucket);
+    else dispatch_fallback<MODE, CLS + 1, CHI>(bucket, prm, pairs, np, lds, slot);
+  }
+}
+
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Persistent launch (one per mode and class part): every resident wave takes
@@ -1088,12 +1098,13 @@ k_side_persistent(const Params* __restrict__ prm) {
     }
     const int bucket = (int)G(prm->qorder)[lo];
     const uint32_t idx = item - G(qstart)[lo];
-    const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
+    const int cls = bucket_class(bucket);
+    const int ppi = pairs_per_item(bucket_kind(bucket), full ? fallback_class(cls) : cls);
     const uint32_t first = idx * (uint32_t)ppi;
     const uint32_t cnt = G(full ? prm->fbcount : prm->dbcount)[bucket];
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
     const uint32_t* list = (full ? prm->fbsorted : prm->dbsorted) + G(prm->bstart)[bucket] + first;
-    if (full) dispatch<kTbFull, MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
+    if (full) dispatch_fallback<MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
     else dispatch<kTbDefer, MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
   }
 }
@@ -1141,6 +1152,8 @@ template <int KIND, int CLS, int MODE>
 __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) void k_side_bucket(const Params* __restrict__ prm) {
   constexpr int bucket = bucket_id(KIND, CLS, MODE);
   constexpr int ppi = pairs_per_item(KIND, CLS);
+  constexpr int FBC = fallback_class(CLS);
+  constexpr int ppf = pairs_per_item(KIND, FBC);
   extern __shared__ uint32_t smem[];
   const int wave = uni((int)(threadIdx.x >> 6));
   const int slot_id = blockIdx.x * kWavesPerBlock + wave;
@@ -1148,7 +1161,11 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) v
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
   const uint32_t nfb = G(prm->fbcount)[bucket], ndb = G(prm->dbcount)[bucket];
-  const uint32_t ifb = (nfb + ppi - 1) / ppi;
+  // a list that fills every resident wave several times over is bound by
+  // work, not by the latency of its last items: it stays in the pair's own
+  // class (no extra dummy rows)
+  const bool alt = FBC != CLS && 4u * ((nfb + ppi - 1) / ppi) <= (uint32_t)prm->n_slots;
+  const uint32_t ifb = alt ? (nfb + ppf - 1) / ppf : (nfb + ppi - 1) / ppi;
   const uint32_t items = ifb + (ndb + ppi - 1) / ppi;
   if ((uint32_t)slot_id >= items) return;
   const uint32_t bs = G(prm->bstart)[bucket];
@@ -1158,9 +1175,15 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) v
     const uint32_t it = wave_uniform(v);
     if (it >= items) break;
     if (it < ifb) {
-      const uint32_t first = it * ppi;
-      const int np = (int)((nfb - first) < (uint32_t)ppi ? (nfb - first) : (uint32_t)ppi);
-      run_one<kTbFull, CLS, KIND, MODE>(prm, prm->fbsorted + bs + first, np, lds, slot, bucket);
+      const uint32_t per = alt ? ppf : ppi;
+      const uint32_t first = it * per;
+      const int np = (int)((nfb - first) < per ? (nfb - first) : per);
+      if constexpr (FBC != CLS) {
+        if (alt) run_one<kTbFull, FBC, KIND, MODE>(prm, prm->fbsorted + bs + first, np, lds, slot, bucket);
+        else run_one<kTbFull, CLS, KIND, MODE>(prm, prm->fbsorted + bs + first, np, lds, slot, bucket);
+      } else {
+        run_one<kTbFull, CLS, KIND, MODE>(prm, prm->fbsorted + bs + first, np, lds, slot, bucket);
+      }
     } else {
       const uint32_t first = (it - ifb) * ppi;
       const int np = (int)((ndb - first) < (uint32_t)ppi ? (ndb - first) : (uint32_t)ppi);

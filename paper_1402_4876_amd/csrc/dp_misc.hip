@@ -114,9 +114,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const Params* __restrict_
       } else {
         const int cls = prm->class_of_m[m];
         const int d0 = class_lanes(cls) * class_rows(cls) - m;
+        // the 16-bit bounds hold for the fallback class's dummy rows too
+        // (at least as many as the pair's own class)
+        const int fbc = fallback_class(cls);
+        const int d0k = class_lanes(fbc) * class_rows(fbc) - m;
         int kind;
         if (prm->flags & kForceInt32) kind = kK32;
-        else kind = int16_safe(m, n, md, d0, prm->sa, prm->sb, prm->so, prm->se, h0) ? kK16 : kK16Sat;
+        else kind = int16_safe(m, n, md, d0k, prm->sa, prm->sb, prm->so, prm->se, h0) ? kK16 : kK16Sat;
         b = (uint32_t)(bucket_id(kind, cls, md) * kSubBins + sub_bin(cls, d0));
         atomicAdd(&hist[b], 1u);
       }
@@ -206,7 +210,8 @@ __global__ __launch_bounds__(kScanThreads) void k_sidescan(const Params* __restr
     if (q < kNumBuckets) {
       const int b = (int)prm->qorder[q];
       if (persistent_bucket(b)) {
-        const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), bucket_class(b));
+        const int cls = list ? bucket_class(b) : fallback_class(bucket_class(b));
+        const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), cls);
         items = (count[b] + ppi - 1) / ppi;
       }
     }

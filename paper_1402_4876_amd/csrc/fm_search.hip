@@ -6,6 +6,7 @@
 
 #include "ctx.h"
 #include "fm_common.h"
+#include "fm_match.h"
 #include "mica_fm.h"
 
 namespace mica {
@@ -28,51 +29,8 @@ struct FmSearchArgs {
   int64_t* cand;
 };
 
-__device__ __forceinline__ uint32_t base_at(const uint32_t* w, uint64_t p) {
-  return (w[p >> 4] >> (2 * (uint32_t)(p & 15))) & 3u;
-}
-
-// 16 bases from base position p (zeros past the last word)
-__device__ __forceinline__ uint32_t bases16(const uint32_t* w, uint64_t p, uint64_t nwords) {
-  const uint64_t i = p >> 4;
-  const uint32_t s = 2 * (uint32_t)(p & 15);
-  const uint32_t lo = i < nwords ? w[i] : 0u;
-  if (s == 0) return lo;
-  const uint32_t hi = i + 1 < nwords ? w[i + 1] : 0u;
-  return __builtin_amdgcn_alignbit(hi, lo, s);
-}
-
-// bit 2t set where symbol t of the two 16-base words differs
-__device__ __forceinline__ uint32_t diff_mask(uint32_t a, uint32_t b) {
-  const uint32_t x = a ^ b;
-  return (x | (x >> 1)) & 0x55555555u;
-}
-
-// difference mask of 16 read bases from ro + t and reference bases from
-// p + t, the symbols at or past len cleared
-__device__ __forceinline__ uint32_t chunk_diff(const FmSearchArgs& A, uint64_t ro, uint64_t p, int t, int len) {
-  uint32_t mm = diff_mask(bases16(A.reads2b, ro + t, A.read_words), bases16(A.ix.ref2b, p + t, A.ix.ref_words));
-  const int rem = len - t;
-  return rem < 16 ? mm & ((1u << (2 * rem)) - 1u) : mm;
-}
-
-// mismatches between read bases [ro, ro + len) and reference bases
-// [p, p + len); the count stops growing once it exceeds lim
-__device__ __forceinline__ int mismatches(const FmSearchArgs& A, uint64_t ro, uint64_t p, int len, int lim) {
-  int d = 0;
-  for (int t = 0; t < len; t += 16) {
-    d += __popc(chunk_diff(A, ro, p, t, len));
-    if (d > lim) break;
-  }
-  return d;
-}
-
-// read bases [ro, ro + len) equal reference bases [p, p + len)
-__device__ __forceinline__ bool exact(const FmSearchArgs& A, uint64_t ro, uint64_t p, int len) {
-  uint32_t acc = 0;
-  for (int t = 0; t < len; t += 16) acc |= chunk_diff(A, ro, p, t, len);
-  return acc == 0;
-}
+using fm::base_at;
+using fm::diff_mask;
 
 // Occ(c, i): occurrences of base c in BWT rows [0, i)
 __device__ __forceinline__ uint32_t occ(const FmIndex& ix, uint32_t c, uint32_t i) {
@@ -113,6 +71,7 @@ __global__ __launch_bounds__(256) void k_fm_search(FmSearchArgs A) {
     if (m < k + 1 || m > MICA_MAX_READ_LEN) st = MICA_ST_LEN_LIMIT;
     else if (ro > A.reads_len || (uint64_t)m > A.reads_len - ro) st = MICA_ST_READ_OOB;
   }
+  const fm::Stretch S{A.reads2b, A.read_words, A.ix.ref2b, A.ix.ref_words};
   int rep = 0, best = 0x7FFFFFFF, nb = 0, nh = 0;
   int64_t bp = 0x7FFFFFFFFFFFFFFFll;
   if (live && st == 0 && j <= k) {
@@ -138,15 +97,15 @@ __global__ __launch_bounds__(256) void k_fm_search(FmSearchArgs A) {
         bool mine = true;
         if (j >= 1) {
           const int e0 = (int)((int64_t)m / (k + 1));
-          mine = !exact(A, ro, (uint64_t)p, e0);
+          mine = !fm::exact(S, ro, (uint64_t)p, e0);
         }
         if (j >= 2 && mine) {
           const int a1 = (int)((int64_t)m / (k + 1));
           const int e1 = (int)((int64_t)2 * m / (k + 1));
-          mine = !exact(A, ro + a1, (uint64_t)p + a1, e1 - a1);
+          mine = !fm::exact(S, ro + a1, (uint64_t)p + a1, e1 - a1);
         }
         if (!mine) continue;
-        const int d = mismatches(A, ro, (uint64_t)p, m, k);
+        const int d = fm::mismatches(S, ro, (uint64_t)p, m, k);
         if (d > k) continue;
         ++nh;
         if (d < best) {

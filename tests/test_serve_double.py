@@ -8,6 +8,10 @@
 - The CPU oracle itself (oracle/gotoh.c, oracle/kmm.c) built with
   AddressSanitizer + UndefinedBehaviorSanitizer and run on hand examples,
   edge cases and random batches by a small driver.
+- The few-mismatch search's base comparisons
+  (paper_1402_4876_amd/csrc/fm_match.h, the device helpers of the search
+  kernel) built as host code with AddressSanitizer +
+  UndefinedBehaviorSanitizer and compared with base-by-base counts.
 """
 import os
 import subprocess
@@ -64,3 +68,9 @@ def test_oracle_under_asan_ubsan():
                  [os.path.join(ORACLE, "gotoh.c"), os.path.join(ORACLE, "kmm.c")], ASAN)
     out = _run(exe, {"ASAN_OPTIONS": "detect_leaks=1:abort_on_error=1"})
     assert "oracle under sanitizers: ok" in out
+
+
+def test_search_base_comparisons_under_asan_ubsan():
+    exe = _build("fm_match_asan", [os.path.join(ROOT, "tests", "fm_match_check.cpp")], [], ASAN)
+    out = _run(exe, {"ASAN_OPTIONS": "detect_leaks=1:abort_on_error=1", "UBSAN_OPTIONS": "print_stacktrace=1"})
+    assert "stretches ok" in out
