@@ -297,6 +297,34 @@ def serving_bench(n_per_rate=2000, warmup=200, pool_reads=200_000, slots=4, frac
     out = {"reference_bases": ref_len, "requests_per_rate": n_per_rate, "warmup_requests": warmup,
            "request_pool_reads": pool_reads, "distinct_requests": True,
            "mean_cells_per_request": round(float(cells.mean() * 5000.5), 1), "submitter": "library replay thread"}
+    # the same reads as one batch through the batch API (the served mix's
+    # own batch rate: three read-length classes, semi-global, full outputs)
+    import torch
+    dev_ref = torch.as_tensor(np.ascontiguousarray(ref).view(np.int32)).cuda()
+    dev_reads = torch.as_tensor(np.ascontiguousarray(words).view(np.int32)).cuda()
+    dwo, dwl = torch.as_tensor(wo.view(np.int64)).cuda(), torch.as_tensor(wl).cuda()
+    dro, drl = torch.as_tensor(ro.view(np.int64)).cuda(), torch.as_tensor(rl).cuda()
+    bctx = mica.Context()
+    try:
+        def batch_step():
+            return mica.align(bctx, dev_ref, dwo, dwl, dev_reads, dro, drl, out_cigar=True, cigar_cap=64,
+                              max_read_len=int(rl.max()), max_win_len=int(wl.max()), ref_len=ref_len,
+                              reads_len=len(pool.reads), min_read_len=int(rl.min()))
+        for _ in range(2):
+            batch_step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            batch_step()
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - t1) * 1e3 / 5
+    finally:
+        bctx.close()
+    del dev_ref, dev_reads, dwo, dwl, dro, drl
+    torch.cuda.empty_cache()
+    out["batch_same_reads"] = {"reads": int(len(rl)), "ms": round(bms, 3),
+                               "gcups": round(float(cells.sum()) / (bms * 1e-3) / 1e9, 1)}
+    log("serving: the pool as one batch: %s" % out["batch_same_reads"])
     srv = mica.Server(ref, ref_len, slots=slots)
     sample_ids = []
     try:
@@ -304,6 +332,7 @@ def serving_bench(n_per_rate=2000, warmup=200, pool_reads=200_000, slots=4, frac
         lam, lam_gcups = closed_loop(srv, 2000, 91, 20_000_000)
         out["lambda_max_rps"] = round(lam, 1)
         out["gcups_at_lambda_max"] = round(lam_gcups, 1)
+        out["served_over_batch_same_reads"] = round(lam_gcups / out["batch_same_reads"]["gcups"], 3)
         out["batching"] = {"slots": slots, "rates": []}
         for i, f in enumerate(fracs):
             id0 = 30_000_000 + i * 1_000_000

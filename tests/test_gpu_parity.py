@@ -224,22 +224,11 @@ def test_pack_2bit_on_gpu(ctx):
     assert np.array_equal(w.cpu().numpy().view(np.uint32), mica.pack_codes(codes))
 
 
-@pytest.mark.parametrize("plain", [False, True])
-def test_config1_full_size_sampled(ctx, plain):
-    """The benchmark's batch (10^6 pairs, far more work items than resident waves),
-    through both launch styles: sampled pairs against the oracle, every pair against
-    properties that hold at any size."""
-    b = synth.config1()
-    g = U.run_gpu(ctx, b, SC, max_read_len=150, max_win_len=400, plain=plain)
-    idx = np.sort(np.random.default_rng(8).choice(b.n_pairs, 3000, replace=False))
-    U.assert_same(g, U.run_oracle(b, SC, idx=idx), idx=idx, what="c1 sample")
-    assert not g["status"].any()
-    assert (g["read_start"] == 0).all() and (g["read_end"] == 150).all()
-    assert (g["score"] <= 150).all()
-    assert (g["ref_start"] <= g["ref_end"]).all() and (g["ref_end"] <= 400).all()
-    # the CIGAR consumes exactly the reported spans
+def _spans_consistent(g):
+    """Every pair's CIGAR consumes exactly its reported read and window spans."""
     cig = g["cigar"].astype(np.uint32)
     nc = g["n_cigar"]
+    assert (nc >= 0).all()
     col = np.arange(cig.shape[1])[None, :] < nc[:, None]
     L = np.where(col, cig >> 4, 0)
     op = cig & 15
@@ -247,6 +236,53 @@ def test_config1_full_size_sampled(ctx, plain):
     ref_span = (L * ((op == 0) | (op == 2))).sum(axis=1)
     assert np.array_equal(read_span, g["read_end"] - g["read_start"])
     assert np.array_equal(ref_span, g["ref_end"] - g["ref_start"])
+
+
+@pytest.mark.parametrize("launch", ["one_class", "persistent", "plain"])
+def test_config1_full_size_sampled(ctx, launch):
+    """The benchmark's batch (10^6 pairs, far more work items than resident waves):
+    in the launch the benchmark times (one read length: its class kernel, as with
+    min_read_len = max_read_len = 150) and through both general launch styles;
+    sampled pairs against the oracle, every pair against properties that hold
+    at any size."""
+    b = synth.config1()
+    g = U.run_gpu(ctx, b, SC, max_read_len=150, max_win_len=400, plain=launch == "plain",
+                  min_read_len=150 if launch == "one_class" else 0)
+    idx = np.sort(np.random.default_rng(8).choice(b.n_pairs, 3000, replace=False))
+    U.assert_same(g, U.run_oracle(b, SC, idx=idx), idx=idx, what="c1 sample")
+    assert not g["status"].any()
+    assert (g["read_start"] == 0).all() and (g["read_end"] == 150).all()
+    assert (g["score"] <= 150).all()
+    assert (g["ref_start"] <= g["ref_end"]).all() and (g["ref_end"] <= 400).all()
+    _spans_consistent(g)
+
+
+def test_config2_full_size_sampled(ctx):
+    """The 5 x 10^5-pair local workload as the benchmark runs it (one class):
+    sampled pairs against the oracle, every pair against local-mode properties."""
+    b = synth.config2()
+    g = U.run_gpu(ctx, b, SC, max_read_len=150, max_win_len=int(b.win_len.max()), min_read_len=150)
+    idx = np.sort(np.random.default_rng(9).choice(b.n_pairs, 2000, replace=False))
+    U.assert_same(g, U.run_oracle(b, SC, idx=idx), idx=idx, what="c2 sample")
+    assert not (g["status"] & ~1).any()
+    assert (g["score"] >= 0).all() and (g["score"] <= 150).all()
+    assert (g["read_start"] <= g["read_end"]).all() and (g["read_end"] <= 150).all()
+    _spans_consistent(g)
+
+
+def test_config3_full_size_sampled(ctx):
+    """The 2 x 10^6-pair mixed workload in its persistent launch: sampled pairs
+    against the oracle (both modes, every read length), every pair against
+    properties that hold at any size."""
+    b = synth.config3()
+    g = U.run_gpu(ctx, b, SC, max_read_len=int(b.read_len.max()), max_win_len=int(b.win_len.max()))
+    idx = np.sort(np.random.default_rng(10).choice(b.n_pairs, 2000, replace=False))
+    U.assert_same(g, U.run_oracle(b, SC, idx=idx), idx=idx, what="c3 sample")
+    assert not (g["status"] & ~1).any()
+    assert (g["read_end"] <= b.read_len).all() and (g["ref_end"] <= b.win_len).all()
+    sg = b.mode == 0
+    assert (g["read_start"][sg] == 0).all() and (g["read_end"][sg] == b.read_len[sg]).all()
+    _spans_consistent(g)
 
 
 def test_min_read_len_hint(ctx):
