@@ -34,19 +34,21 @@ OPS_PER_CELL = {("sg", True): 13, ("sg", False): 9, ("local", True): 16, ("local
                 ("ext", True): 16, ("ext", False): 11}
 EXT_CLIP = 5  # clipping penalty of the seed-extension workload
 
-# HBM bytes per launch of the dominant fill kernel from two rocprofv3 passes
-# (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a 1 GiB
-# device copy (2048 bytes per FETCH_SIZE unit, 1024 per WRITE_SIZE unit).
-# They hold only for the kernel source they were taken on, identified by the
-# SHA-256 of the fill kernel's sources; for any other source the bench line
-# reports traffic as null.
-# The traffic figures hold only for the build they were taken on: the fill
-# kernels' sources and the build script (compiler flags, resident-wave
-# targets live in the sources), identified by one SHA-256; for any other
-# build the bench line reports traffic as null.
+# HBM bytes moved by the DP launches of one step, from two rocprofv3 passes
+# (FETCH_SIZE, WRITE_SIZE) of this script, scaled by what the counters read
+# for a 1 GiB device copy (2048 bytes per FETCH_SIZE unit, 1024 per
+# WRITE_SIZE unit); the summaries are under profiles/.  They hold only for
+# the build they were taken on: the DP kernels' sources and the build script
+# (compiler flags; resident-wave targets live in the sources), identified by
+# one SHA-256; for any other build the bench line reports traffic as null.
 MEASURED_TRAFFIC = {
-    # config: (build sha256, fetch bytes, write bytes); for the extension
-    # workload the sums over its fill launches and re-run
+    # config: (build sha256, fetch bytes, write bytes)
+    "c1": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 4367725568, 4489369728),
+    "c2": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 3419169408, 8414166240),
+    "c3": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 15777042816, 11696224160),
+    "ext": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 5836247040, 2077916768),
+    # the search kernel: its own sources (fm_source_sha)
+    "bwt": ("7bd545de6e0822eccd77eca98f46c872f8b688666e356e26c45b01fc1e9a9b7b", 12810119168, 26541056),
 }
 
 
@@ -63,13 +65,14 @@ def kernel_source_sha():
     """SHA-256 of every source the DP fill kernels are built from, plus the build script."""
     csrc = os.path.join(ROOT, "paper_1402_4876_amd", "csrc")
     files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
-                   if f.endswith(".h") or f.startswith(("fill_", "persistent_", "side_")) or f == "dp_misc.hip")
+                   if f in ("dp_common.h", "dp_fill.h", "band.h", "plan.h", "dp_misc.hip") or
+                   f.startswith(("fill_", "persistent_", "side_")))
     return _sha_of(files + [os.path.join(ROOT, "paper_1402_4876_amd", "build.py")])
 
 
 def fm_source_sha():
     csrc = os.path.join(ROOT, "paper_1402_4876_amd", "csrc")
-    return _sha_of([os.path.join(csrc, f) for f in ("fm_search.hip", "fm_common.h")] +
+    return _sha_of([os.path.join(csrc, f) for f in ("fm_search.hip", "fm_common.h", "fm_match.h")] +
                    [os.path.join(ROOT, "paper_1402_4876_amd", "build.py")])
 
 
