@@ -309,24 +309,27 @@ def serving_bench(n_per_rate=2000, warmup=200, pool_reads=200_000, slots=4, frac
     dro, drl = torch.as_tensor(ro.view(np.int64)).cuda(), torch.as_tensor(rl).cuda()
     bctx = mica.Context()
     try:
-        def batch_step():
+        def step():
             return mica.align(bctx, dev_ref, dwo, dwl, dev_reads, dro, drl, out_cigar=True, cigar_cap=64,
                               max_read_len=int(rl.max()), max_win_len=int(wl.max()), ref_len=ref_len,
                               reads_len=len(pool.reads), min_read_len=int(rl.min()))
         for _ in range(2):
-            batch_step()
+            step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(5):
-            batch_step()
+            step()
         torch.cuda.synchronize()
         bms = (time.perf_counter() - t1) * 1e3 / 5
     finally:
         bctx.close()
     del dev_ref, dev_reads, dwo, dwl, dro, drl
     torch.cuda.empty_cache()
+    # (the server runs the default plan too: a plan autotuned on these reads
+    # made the one batch faster, 2,963 -> 3,244 GCUPS, but not the served
+    # stream, whose batches are about 17,000 reads)
     out["batch_same_reads"] = {"reads": int(len(rl)), "ms": round(bms, 3),
-                               "gcups": round(float(cells.sum()) / (bms * 1e-3) / 1e9, 1)}
+                               "gcups": round(float(cells.sum()) / (bms * 1e-3) / 1e9, 1), "plan": "default"}
     log("serving: the pool as one batch: %s" % out["batch_same_reads"])
     srv = mica.Server(ref, ref_len, slots=slots)
     sample_ids = []

@@ -356,6 +356,15 @@ mica_status_t mica_server_fetch(mica_server_t server, uint64_t request_id, int32
 mica_status_t mica_server_stats(mica_server_t server, double *p50_s, double *p99_s, double *gcups);
 mica_status_t mica_server_reset_stats(mica_server_t server);
 
+/* Give every slot's context a plan file (mica_ctx_save_plan; the kernel
+ * plan per read-length range, e.g. tuned by mica_ctx_autotune on requests
+ * like the expected ones; Methods, pipelining & load balancing).  Waits
+ * until the queued and running batches have finished and holds submissions
+ * meanwhile; later batches use the plan.  Results do not depend on the
+ * plan.  MICA_ERR_INVALID_ARG for a file the contexts refuse (another
+ * device kind, a malformed table). */
+mica_status_t mica_server_load_plan(mica_server_t server, const char *path);
+
 /* Finish the queued work, stop the worker and free everything. */
 mica_status_t mica_server_destroy(mica_server_t server);
 

@@ -46,7 +46,7 @@ EXPORTS = ("mica_ctx_create", "mica_ctx_destroy", "mica_dp_align_batch", "mica_p
            "mica_server_reset_stats", "mica_server_destroy", "mica_last_error", "mica_fm_suffix_array",
            "mica_fm_create", "mica_fm_destroy", "mica_fm_info", "mica_fm_search", "mica_pipe_create",
            "mica_pipe_run", "mica_pipe_destroy", "mica_dp_align_batch_noalloc", "mica_measure_valu_peak",
-           "mica_server_replay", "mica_server_replay_wait")
+           "mica_server_replay", "mica_server_replay_wait", "mica_server_load_plan")
 
 
 class Scoring(ctypes.Structure):
@@ -160,6 +160,7 @@ def load():
     lib.mica_server_submit.argtypes = [P, ctypes.c_uint64, P, P, P, P, P, P, i64, ctypes.c_double]
     lib.mica_server_replay.argtypes = [P, P, P, P, P, P, P, P, P, P, i64, ctypes.c_uint64]
     lib.mica_server_replay_wait.argtypes = [P, D]
+    lib.mica_server_load_plan.argtypes = [P, ctypes.c_char_p]
     lib.mica_server_poll.argtypes = [P, P, i64, ctypes.POINTER(i64)]
     lib.mica_server_fetch.argtypes = [P, ctypes.c_uint64, P, P, P, P, P, P, i32, P, P]
     lib.mica_server_stats.argtypes = [P, D, D, D]

@@ -63,6 +63,13 @@ class Backend {
   virtual bool finish(std::string* err) = 0;
   virtual const int32_t* outputs() const = 0;
   virtual const uint32_t* cigars() const = 0;
+  // Take a plan file (the library's per-read-length kernel plan) for the
+  // slot's later batches; called only while the slot is idle.
+  virtual bool load_plan(const char* path, std::string* err) {
+    (void)path;
+    (void)err;
+    return true;
+  }
 };
 
 struct Limits {
@@ -101,6 +108,27 @@ class Core {
 
   double now() const { return now_s(t0_); }
   const Limits& limits() const { return lim_; }
+
+  // Load a plan file into every slot once the queued and running batches
+  // have finished; submissions wait meanwhile (the lock is held throughout).
+  mica_status_t load_plan(const char* path, std::string* err) {
+    if (!path) return set(err, MICA_ERR_INVALID_ARG, "NULL plan path");
+    std::unique_lock<std::mutex> lk(mu_);
+    idle_cv_.wait(lk, [this] {
+      if (!queue_.empty()) return false;
+      for (char b : slot_busy_)
+        if (b) return false;
+      return true;
+    });
+    for (auto& be : backends_)
+      if (!be->load_plan(path, err)) return MICA_ERR_INVALID_ARG;
+    ++plans_loaded_;
+    return MICA_OK;
+  }
+  int64_t plans_loaded() {
+    std::lock_guard<std::mutex> g(mu_);
+    return plans_loaded_;
+  }
 
   // Validate and copy a request into the queue.  Returns MICA_OK or an error
   // with its text in *err.
@@ -366,6 +394,7 @@ class Core {
       last_done_ = std::max(last_done_, t);
       slot_busy_[(size_t)s] = 0;
       batches_run_[(size_t)s]++;
+      idle_cv_.notify_all();
     }
   }
 
@@ -374,6 +403,8 @@ class Core {
   std::chrono::steady_clock::time_point t0_;
   std::mutex mu_;
   std::condition_variable cv_;
+  std::condition_variable idle_cv_;  // a slot finished a batch
+  int64_t plans_loaded_ = 0;
   std::deque<std::shared_ptr<Request>> queue_;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> live_;  // submitted, not fetched
   std::deque<uint64_t> done_ids_;

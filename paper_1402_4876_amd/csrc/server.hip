@@ -208,6 +208,11 @@ class GpuSlot : public serve::Backend {
   const uint32_t* cigars() const override {
     return (const uint32_t*)(h_out_ + align_up((size_t)7 * kSlotPairs * 4, 256));
   }
+  bool load_plan(const char* path, std::string* err) override {
+    if (mica_ctx_load_plan(ctx_, path) == MICA_OK) return true;
+    *err = mica_last_error();
+    return false;
+  }
 
  private:
   int device_, index_;
@@ -362,6 +367,13 @@ mica_status_t mica_server_stats(mica_server_t s, double* p50_s, double* p99_s, d
   if (!s) return fail(MICA_ERR_INVALID_ARG, "server is NULL");
   std::string err;
   const mica_status_t st = s->core->stats(p50_s, p99_s, gcups, &err);
+  return core_fail(st, err);
+}
+
+mica_status_t mica_server_load_plan(mica_server_t s, const char* path) {
+  if (!s) return fail(MICA_ERR_INVALID_ARG, "server is NULL");
+  std::string err;
+  const mica_status_t st = s->core->load_plan(path, &err);
   return core_fail(st, err);
 }
 

@@ -7,6 +7,7 @@ submit); outputs come back as numpy arrays.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -86,6 +87,11 @@ class Server:
         finally:
             self._replay_keep = None
         return lag.value
+
+    def load_plan(self, path):
+        """Give every slot the kernel plan in `path` (Context.save_plan); waits
+        for the queued and running batches, holds submissions meanwhile."""
+        _lib.check(_lib.load().mica_server_load_plan(self._h, os.fsencode(path)))
 
     def poll(self, cap=4096):
         ids = np.zeros(cap, np.uint64)

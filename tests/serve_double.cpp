@@ -168,6 +168,16 @@ class HostSlot : public Backend {
   }
   const int32_t* outputs() const override { return out_.data(); }
   const uint32_t* cigars() const override { return cig_.data(); }
+  // a plan is taken only while no slot runs a batch
+  bool load_plan(const char* path, std::string* err) override {
+    if (in_flight_->load() != 0) {
+      *err = "plan loaded during a batch";
+      return false;
+    }
+    plans_.push_back(path);
+    return true;
+  }
+  std::vector<std::string> plans_;
 
  private:
   void delay() {
@@ -412,7 +422,27 @@ int main() {
     CHECK(rig.core->replay_wait(&lag, &err) == MICA_OK && lag >= 0 && lag < 0.05, "replay lag %.4f s", lag);
     collect_and_check(*rig.core, w, reqs, 20000, "replayed");
   }
-  // 5. stopping finishes what is queued
+  // 5. a plan reaches every slot while none runs a batch, with submissions
+  //    from another thread going on; every request still exact
+  {
+    Rig rig(w, 3, lim, 1500);
+    const auto reqs = make_requests(w, 240, 16, 120);
+    std::vector<Req> a(reqs.begin(), reqs.begin() + 120), b(reqs.begin() + 120, reqs.end());
+    std::thread t1([&] { submit_all(*rig.core, w, a, 70000); });
+    std::string err;
+    for (int k = 0; k < 3; ++k) {
+      std::this_thread::sleep_for(std::chrono::milliseconds(5));
+      CHECK(rig.core->load_plan("plan.json", &err) == MICA_OK, "plan %d loads: %s", k, err.c_str());
+    }
+    t1.join();
+    CHECK(rig.core->load_plan(nullptr, &err) == MICA_ERR_INVALID_ARG, "NULL plan path refused");
+    submit_all(*rig.core, w, b, 80000);
+    collect_and_check(*rig.core, w, a, 70000, "around plan loads");
+    collect_and_check(*rig.core, w, b, 80000, "after plan loads");
+    CHECK(rig.core->plans_loaded() == 3, "three plans loaded (%lld)", (long long)rig.core->plans_loaded());
+    CHECK(rig.log.size() > 0, "batches ran");
+  }
+  // 6. stopping finishes what is queued
   {
     Rig rig(w, 2, lim, 1000);
     const auto reqs = make_requests(w, 50, 15, 100);

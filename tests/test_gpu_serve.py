@@ -169,3 +169,36 @@ def test_tight_hbm_budget_serves_long_windows():
         srv.close()
     g = _concat(got, list(range(len(reqs))))
     U.assert_same(g, U.run_oracle(b, SC, idx=np.concatenate(reqs)), what="tight budget")
+
+
+def test_plan_loaded_into_the_slots(served, tmp_path):
+    """A kernel plan given to the server (loaded while requests are queued and
+    running, which it waits for) changes which kernels run but not the
+    results; a file the contexts refuse is an error."""
+    import paper_1402_4876_amd as mica
+    b, ref_words, reads_words, reqs, res, _ = served
+    ctx = mica.Context()
+    try:
+        ctx.set_plan(1, 256, 64, 4)  # every read of the mix in the 64-lane, 4-row class
+        plan = tmp_path / "plan.json"
+        ctx.save_plan(str(plan))
+    finally:
+        ctx.close()
+    bad = tmp_path / "bad.json"
+    bad.write_text("{not a plan")
+    srv = mica.Server(ref_words, len(b.ref), slots=3, hbm_budget_bytes=4 << 30)
+    try:
+        for r in range(10):
+            _submit(srv, b, reads_words, 700 + r, reqs[r])
+        srv.load_plan(str(plan))
+        for r in range(10, 20):
+            _submit(srv, b, reads_words, 700 + r, reqs[r])
+        got = _wait(srv, [700 + r for r in range(20)])
+        with pytest.raises(mica.MicaError):
+            srv.load_plan(str(bad))
+        with pytest.raises(mica.MicaError):
+            srv.load_plan(str(tmp_path / "missing.json"))
+    finally:
+        srv.close()
+    for r in range(20):
+        U.assert_equal_outputs(got[700 + r], res[100 + r], "request %d under the loaded plan" % r)
