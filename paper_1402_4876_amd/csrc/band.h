@@ -169,7 +169,8 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
 #pragma unroll
   for (int h = 0; h < NP; ++h)
     if (valid[h])
-      lds[kRedOff + (bg * NP + h) * 4 + 3] = (uint32_t)(dlo[h] + 32768) | ((uint32_t)(act[h] ? W[h] : 0) << 16) |
+      lds[kRedOff + (bg * NP + h) * 4 + 3] = (uint32_t)(dlo[h] + 32768) |
+                                             ((uint32_t)(act[h] || dfr[h] ? W[h] : 0) << 16) |
                                              (act[h] ? 1u << 24 : 0u) | (fb[h] ? 1u << 25 : 0u) |
                                              (sat[h] ? 1u << 26 : 0u) | (dfr[h] ? 1u << 27 : 0u);
   const int rows_u = wave_max_int(rows_l);
@@ -425,8 +426,16 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
         G(prm->score)[p_] = (int)red[q * 4 + 0] + d0_;
         G(prm->read_end)[p_] = (int)red[q * 4 + 1];
         G(prm->ref_end)[p_] = (int)red[q * 4 + 2];
-        const uint32_t pos = atomicAdd(&prm->dbcount[bucket], 1u);
-        G(prm->dbsorted)[G(prm->bstart)[bucket] + pos] = (uint32_t)p_;
+        // two lists in the bucket's range, so that an item of the later
+        // refill runs the strips its own pairs need: up to 32 diagonals
+        // from the start, wider from the end
+        if (((w3 >> 16) & 0xFFu) <= 32u) {
+          const uint32_t pos = atomicAdd(&prm->dbcount[bucket], 1u);
+          G(prm->dbsorted)[G(prm->bstart)[bucket] + pos] = (uint32_t)p_;
+        } else {
+          const uint32_t pos = atomicAdd(&prm->dbwide[bucket], 1u);
+          G(prm->dbsorted)[G(prm->bstart)[bucket] + G(prm->bcount)[bucket] - 1u - pos] = (uint32_t)p_;
+        }
       }
     } else {
       const int score = (int)red[q * 4 + 0] + d0_;

@@ -43,7 +43,8 @@ constexpr size_t kFbcount = kSfill + kNumSubBuckets;
 constexpr size_t kSidehead = kFbcount + kNumBuckets;
 constexpr size_t kFbqstart = kSidehead + kNumBuckets;  // kNumBuckets + 1 entries
 constexpr size_t kDbcount = kFbqstart + kNumBuckets + 8;
-constexpr size_t kDbqstart = kDbcount + kNumBuckets;  // kNumBuckets + 1 entries
+constexpr size_t kDbwide = kDbcount + kNumBuckets;
+constexpr size_t kDbqstart = kDbwide + kNumBuckets;  // kNumBuckets + 1 entries
 constexpr size_t kWords = kDbqstart + kNumBuckets + 8;
 }  // namespace small
 

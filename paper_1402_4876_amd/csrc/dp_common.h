@@ -119,18 +119,16 @@ constexpr uint32_t kOutCigar = 1u << 1;
 constexpr uint32_t kForceInt32 = 1u << 8;
 
 // LDS per wave (32-bit words): during the fill, a window-selector ring of 256
-// columns for each of up to 4 lane groups and the per-lane local-best
-// candidates; after it, the banded traceback's read and window codes in the
-// same space.  The per-pair results (shifted score, i*, j*) and the
+// columns for each of up to 4 lane groups; after it, the banded traceback's
+// read and window codes in the same space.  The per-pair results (shifted score, i*, j*) and the
 // extension's end-to-end candidates sit at the top.
 constexpr int kRing = 256;
 constexpr int kRingWords = 4 * kRing;
-constexpr int kCandWords = 64 * 2 * 3;
 constexpr int kLdsWaveWords = 2048;
 constexpr int kRedOff = kLdsWaveWords - 64;  // 8 pairs x 4 words
 constexpr int kGslOff = kLdsWaveWords - 32;  // 8 pairs x 2 words
 constexpr int kBandWords = kRedOff;          // band codes: [0, kRedOff)
-static_assert(kRingWords + kCandWords <= kRedOff, "fill areas below the results");
+static_assert(kRingWords <= kRedOff, "fill areas below the results");
 constexpr int kWavesPerBlock = 4;
 // widest band of the banded traceback (diagonals); wider pairs are traced
 // back from a full fill of direction bits instead.  Bands up to
@@ -188,8 +186,10 @@ struct Params {
   uint32_t* fbcount;           // [kNumBuckets] fb pairs per bucket
   uint32_t* fbsorted;          // [n_pairs] fb pairs, in their bucket's range of `sorted`
   uint32_t* fbqstart;          // [kNumBuckets + 1] first fb item of each queue position
-  uint32_t* dbcount;           // [kNumBuckets] db pairs per bucket
-  uint32_t* dbsorted;          // [n_pairs] db pairs, in their bucket's range of `sorted`
+  uint32_t* dbcount;           // [kNumBuckets] db pairs of 17-32 diagonals per bucket
+  uint32_t* dbwide;            // [kNumBuckets] db pairs of 33-64 diagonals per bucket
+  uint32_t* dbsorted;          // [n_pairs] db pairs in their bucket's range of `sorted`: 17-32
+                               // diagonals from its start up, 33-64 from its end down
   uint32_t* dbqstart;          // [kNumBuckets + 1] first db item of each queue position
   uint32_t* sidehead;          // [kNumBuckets] next side-list item of each per-bucket side launch
   uint8_t* scratch;            // n_slots * slot_bytes

@@ -1015,6 +1015,22 @@ __device__ __forceinline__ void dispatch_fallback(int bucket, const Params* prm,
 
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Deferred band item idx of a bucket: the items of the pairs with 33-64
+// diagonals first (stored from the end of the bucket's range down), then
+// those of 17-32 (from its start up).  Returns the item's pairs and count.
+__device__ __forceinline__ const uint32_t* deferred_item(const Params* __restrict__ prm, int bucket, uint32_t idx,
+                                                         int ppi, int* np) {
+  const uint32_t nw = G(prm->dbwide)[bucket], nn = G(prm->dbcount)[bucket];
+  const uint32_t iw = (nw + (uint32_t)ppi - 1) / (uint32_t)ppi;
+  const uint32_t bs = G(prm->bstart)[bucket];
+  const bool wide = idx < iw;
+  const uint32_t first = (wide ? idx : idx - iw) * (uint32_t)ppi;
+  const uint32_t cnt = wide ? nw : nn;
+  const uint32_t base = wide ? bs + G(prm->bcount)[bucket] - nw : bs;
+  *np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
+  return prm->dbsorted + base + first;
+}
+
 // Persistent launch (one per mode and class part): every resident wave takes
 // work items from its part of the queue (buckets in descending cost order)
 // until it is empty.
@@ -1099,13 +1115,17 @@ k_side_persistent(const Params* __restrict__ prm) {
     const int bucket = (int)G(prm->qorder)[lo];
     const uint32_t idx = item - G(qstart)[lo];
     const int cls = bucket_class(bucket);
-    const int ppi = pairs_per_item(bucket_kind(bucket), full ? fallback_class(cls) : cls);
-    const uint32_t first = idx * (uint32_t)ppi;
-    const uint32_t cnt = G(full ? prm->fbcount : prm->dbcount)[bucket];
-    const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    const uint32_t* list = (full ? prm->fbsorted : prm->dbsorted) + G(prm->bstart)[bucket] + first;
-    if (full) dispatch_fallback<MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
-    else dispatch<kTbDefer, MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
+    if (full) {
+      const int ppi = pairs_per_item(bucket_kind(bucket), fallback_class(cls));
+      const uint32_t first = idx * (uint32_t)ppi;
+      const uint32_t cnt = G(prm->fbcount)[bucket];
+      const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
+      dispatch_fallback<MODE, CLO, CHI>(bucket, prm, prm->fbsorted + G(prm->bstart)[bucket] + first, np, lds, slot);
+    } else {
+      int np;
+      const uint32_t* list = deferred_item(prm, bucket, idx, pairs_per_item(bucket_kind(bucket), cls), &np);
+      dispatch<kTbDefer, MODE, CLO, CHI>(bucket, prm, list, np, lds, slot);
+    }
   }
 }
 
@@ -1160,13 +1180,14 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) v
   if (slot_id >= prm->n_slots) return;
   uint32_t* lds = smem + wave * kLdsWaveWords;
   uint8_t* slot = prm->scratch + (size_t)slot_id * prm->slot_bytes;
-  const uint32_t nfb = G(prm->fbcount)[bucket], ndb = G(prm->dbcount)[bucket];
+  const uint32_t nfb = G(prm->fbcount)[bucket];
+  const uint32_t idb = (G(prm->dbwide)[bucket] + ppi - 1) / ppi + (G(prm->dbcount)[bucket] + ppi - 1) / ppi;
   // a list that fills every resident wave several times over is bound by
   // work, not by the latency of its last items: it stays in the pair's own
   // class (no extra dummy rows)
   const bool alt = FBC != CLS && 4u * ((nfb + ppi - 1) / ppi) <= (uint32_t)prm->n_slots;
   const uint32_t ifb = alt ? (nfb + ppf - 1) / ppf : (nfb + ppi - 1) / ppi;
-  const uint32_t items = ifb + (ndb + ppi - 1) / ppi;
+  const uint32_t items = ifb + idb;
   if ((uint32_t)slot_id >= items) return;
   const uint32_t bs = G(prm->bstart)[bucket];
   for (;;) {
@@ -1185,9 +1206,9 @@ __global__ __launch_bounds__(256, MICA_BUCKET_WAVES(KIND, CLS, MODE, kTbFull)) v
         run_one<kTbFull, CLS, KIND, MODE>(prm, prm->fbsorted + bs + first, np, lds, slot, bucket);
       }
     } else {
-      const uint32_t first = (it - ifb) * ppi;
-      const int np = (int)((ndb - first) < (uint32_t)ppi ? (ndb - first) : (uint32_t)ppi);
-      run_one<kTbDefer, CLS, KIND, MODE>(prm, prm->dbsorted + bs + first, np, lds, slot, bucket);
+      int np;
+      const uint32_t* list = deferred_item(prm, bucket, it - ifb, ppi, &np);
+      run_one<kTbDefer, CLS, KIND, MODE>(prm, list, np, lds, slot, bucket);
     }
   }
 }

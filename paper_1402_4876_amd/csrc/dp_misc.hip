@@ -39,6 +39,7 @@ __global__ void k_zero(const Params* __restrict__ prm) {
     prm->bhead[i] = 0;
     prm->fbcount[i] = 0;
     prm->dbcount[i] = 0;
+    prm->dbwide[i] = 0;
     prm->sidehead[i] = 0;
   }
   if (i < kNumCounters) prm->counters[i] = 0;
@@ -204,7 +205,6 @@ __global__ __launch_bounds__(kScanThreads) void k_sidescan(const Params* __restr
   const int q = threadIdx.x;
 #pragma unroll 1
   for (int list = 0; list < 2; ++list) {
-    const uint32_t* count = list ? prm->dbcount : prm->fbcount;
     uint32_t* qstart = list ? prm->dbqstart : prm->fbqstart;
     uint32_t items = 0;
     if (q < kNumBuckets) {
@@ -212,7 +212,8 @@ __global__ __launch_bounds__(kScanThreads) void k_sidescan(const Params* __restr
       if (persistent_bucket(b)) {
         const int cls = list ? bucket_class(b) : fallback_class(bucket_class(b));
         const uint32_t ppi = (uint32_t)pairs_per_item(bucket_kind(b), cls);
-        items = (count[b] + ppi - 1) / ppi;
+        items = list ? (prm->dbwide[b] + ppi - 1) / ppi + (prm->dbcount[b] + ppi - 1) / ppi
+                     : (prm->fbcount[b] + ppi - 1) / ppi;
       }
     }
     uint32_t total;

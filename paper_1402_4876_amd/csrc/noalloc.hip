@@ -140,6 +140,7 @@ mica_status_t mica_dp_align_batch_noalloc(const mica_batch_t* b, const mica_scor
   P.fbqstart = sm + small::kFbqstart;
   P.dbsorted = pairs + 4 * kMaxPairs;
   P.dbcount = sm + small::kDbcount;
+  P.dbwide = sm + small::kDbwide;
   P.dbqstart = sm + small::kDbqstart;
   P.bcount = sm + small::kBcount;
   P.bstart = sm + small::kBstart;

@@ -576,6 +576,7 @@ mica_status_t mica_dp_align_batch(mica_ctx_t c, const mica_batch_t* b, const mic
   P.fbqstart = c->d_small + small::kFbqstart;
   P.dbsorted = c->d_pairs + 4 * c->pair_cap;
   P.dbcount = c->d_small + small::kDbcount;
+  P.dbwide = c->d_small + small::kDbwide;
   P.dbqstart = c->d_small + small::kDbqstart;
   P.bcount = small_bcount(c);
   P.bstart = small_bstart(c);
@@ -664,9 +665,11 @@ mica_status_t mica_ctx_last_stats(mica_ctx_t c, void* stream, mica_batch_stats_t
   HIP_TRY(hipMemcpy(fbc, small_fbcount(c), sizeof(fbc), hipMemcpyDeviceToHost));
   out->n_fallback = 0;
   for (int b = 0; b < kNumBuckets; ++b) out->n_fallback += fbc[b];
-  HIP_TRY(hipMemcpy(fbc, c->d_small + small::kDbcount, sizeof(fbc), hipMemcpyDeviceToHost));
   out->n_deferred = 0;
-  for (int b = 0; b < kNumBuckets; ++b) out->n_deferred += fbc[b];
+  for (size_t list : {small::kDbcount, small::kDbwide}) {
+    HIP_TRY(hipMemcpy(fbc, c->d_small + list, sizeof(fbc), hipMemcpyDeviceToHost));
+    for (int b = 0; b < kNumBuckets; ++b) out->n_deferred += fbc[b];
+  }
   return MICA_OK;
 }
 
