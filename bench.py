@@ -43,10 +43,10 @@ EXT_CLIP = 5  # clipping penalty of the seed-extension workload
 # one SHA-256; for any other build the bench line reports traffic as null.
 MEASURED_TRAFFIC = {
     # config: (build sha256, fetch bytes, write bytes)
-    "c1": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 4367725568, 4489369728),
-    "c2": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 3419169408, 8414166240),
-    "c3": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 15777042816, 11696224160),
-    "ext": ("bc3cfff8ec21716b3bb29bc8c4957a86e5efb80380e6a6a1be492d5ba71d1390", 5836247040, 2077916768),
+    "c1": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 4280446464, 4077702912),
+    "c2": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 3162552832, 7894188544),
+    "c3": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 14869808256, 10479191744),
+    "ext": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 5806509312, 2011122784),
     # the search kernel: its own sources (fm_source_sha)
     "bwt": ("7bd545de6e0822eccd77eca98f46c872f8b688666e356e26c45b01fc1e9a9b7b", 12810119168, 26541056),
 }
