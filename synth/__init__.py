@@ -499,3 +499,53 @@ def rebase_windows(batch):
     ref = base_at_packed(batch.ref, pos) if batch.ref_packed else batch.ref[pos]
     ref = np.concatenate([ref, np.zeros(16, np.uint8)])
     return dataclasses.replace(batch, ref=ref, win_off=off, ref_packed=False)
+
+
+def band_mix(n_pairs, mode, seed=0):
+    """Pairs of one mode whose alignments drift from their end diagonal by
+    anything from nothing to far more than the banded traceback takes:
+    reads of 60-150 bases copied from a window with 0-16 substitutions and
+    0-2 indels of 1-10 bases each; a tenth of the reads are unrelated random
+    bases.  Semi-global windows hold the copy with 0-24 extra bases on each
+    side; local reads also carry random flanks of 0-20 bases; extension
+    windows start at the copy and run 32 bases past the read's length, with
+    anchor scores U{19..60}."""
+    rng = rng_for(17, mode, seed)
+    m = rng.integers(60, 151, n_pairs).astype(np.int32)
+    pad = rng.integers(0, 25, n_pairs) if mode != 2 else np.zeros(n_pairs, np.int64)
+    src_len = m + 64  # source stretch per pair, longer than any read drawn from it
+    n = (m + 32 if mode == 2 else src_len + 2 * pad).astype(np.int32)
+    win_off = np.concatenate([[0], np.cumsum(n.astype(np.int64))[:-1]])
+    ref = random_ref(rng, int(n.sum()) + 16)
+    codes = np.zeros((n_pairs, 250), np.uint8)
+    lens = np.zeros(n_pairs, np.int32)
+    for p in range(n_pairs):
+        start = int(win_off[p] + pad[p])
+        src = ref[start: start + int(src_len[p])].copy() if mode != 2 else ref[start: start + int(n[p])].copy()
+        if rng.random() < 0.1:
+            core = rng.integers(0, 4, int(m[p]), dtype=np.uint8)
+        else:
+            core = list(src[: int(m[p])])
+            for _ in range(int(rng.integers(0, 3))):  # indels
+                at = int(rng.integers(1, max(2, len(core) - 1)))
+                ln = int(rng.integers(1, 11))
+                if rng.random() < 0.5:
+                    del core[at: at + ln]
+                else:
+                    core[at:at] = list(rng.integers(0, 4, ln, dtype=np.uint8))
+            core = np.asarray(core[: int(m[p])], np.uint8)
+            for _ in range(int(rng.integers(0, 17))):  # substitutions
+                i = int(rng.integers(0, len(core)))
+                core[i] = (core[i] + rng.integers(1, 4)) % 4
+        if mode == 1:
+            lf, rf = rng.integers(0, 21, 2)
+            core = np.concatenate([rng.integers(0, 4, lf, dtype=np.uint8), core,
+                                   rng.integers(0, 4, rf, dtype=np.uint8)])[:150]
+        lens[p] = len(core)
+        codes[p, : len(core)] = core
+    if mode == 2:
+        n = (lens + 32).astype(np.int32)
+    b = _finish("band_mix", ref, win_off, n, codes[:, : max(int(lens.max()), 1)], lens, np.full(n_pairs, mode))
+    if mode == 2:
+        b.h0 = rng.integers(19, 61, n_pairs).astype(np.int32)
+    return b
