@@ -532,7 +532,7 @@ def pipe_bench(args):
         fq_bytes = os.path.getsize(fq)
         log("wrote %d reads as FASTQ (%.0f MB) in %.1fs" % (b.n_pairs, fq_bytes / 1e6, time.time() - t0))
         pipe = mica.Pipeline(pack_codes(b.ref), len(b.ref), "chrS", k=BWT_K, max_occ=BWT_MAX_OCC, band=PIPE_BAND,
-                             min_score=0, batch_reads=1 << 18, format_threads=8)
+                             min_score=0, batch_reads=args.pipe_batch, format_threads=args.pipe_threads)
         for _ in range(args.warmup):
             pipe.run(fq, sam)
         runs = []
@@ -548,7 +548,8 @@ def pipe_bench(args):
         "metric": "reads/s (FASTQ to SAM, both phases)", "value": round(b.n_pairs / sec, 1), "unit": "reads/s",
         "n_gpus": 1, "steps": len(runs), "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i16", "data": "synthetic",
-        "config": {"workload": WORKLOADS["pipe"][0], "name": "pipe", "reads": b.n_pairs, "batch_reads": 1 << 18,
+        "config": {"workload": WORKLOADS["pipe"][0], "name": "pipe", "reads": b.n_pairs, "batch_reads": args.pipe_batch,
+                   "format_threads": args.pipe_threads,
                    "fastq_mb": round(fq_bytes / 1e6, 1), "sam_mb": round(sam_bytes / 1e6, 1)},
         "stages_s": {"parse": round(st["parse_seconds"], 3), "gpu": round(st["gpu_seconds"], 3),
                      "format_write": round(st["format_seconds"], 3), "wall": round(st["seconds"], 3)},
@@ -585,6 +586,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4, help="in-flight slots of the serving measurement")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (no batch step)")
     ap.add_argument("--no-fifo", action="store_true", help="skip the FIFO serving baseline")
+    ap.add_argument("--pipe-batch", type=int, default=1 << 18, help="reads per batch of the host pipeline")
+    ap.add_argument("--pipe-threads", type=int, default=8, help="SAM formatting threads of the host pipeline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
