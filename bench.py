@@ -586,6 +586,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4, help="in-flight slots of the serving measurement")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (no batch step)")
     ap.add_argument("--no-fifo", action="store_true", help="skip the FIFO serving baseline")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="c1 only: skip the short runs of c2, c3 and the extensions appended to its line")
     ap.add_argument("--pipe-batch", type=int, default=1 << 18, help="reads per batch of the host pipeline")
     ap.add_argument("--pipe-threads", type=int, default=8, help="SAM formatting threads of the host pipeline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -799,8 +801,49 @@ def main():
         res["parity_sample"] = parity
         if served is not None:
             res["serving"]["parity_sample"] = serving_parity(*served)
+    if args.config == "c1" and not args.no_other_workloads and not args.pairs:
+        res["other_workloads"] = other_workloads()
     print(json.dumps(res), flush=True)
     return 0
+
+
+def other_workloads(steps=5, warmup=2, timeout_s=420):
+    """Short runs of the other DP workloads (c2, c3 with its plain-launch
+    comparison, the seed extensions), each in a child process after the c1
+    measurement, so that one bench invocation reports every DP workload.
+    A failed or timed-out run is reported as such; it never fails the c1 line."""
+    import subprocess
+    out = {}
+    for cfg in ("c2", "c3", "ext"):
+        cmd = [sys.executable, os.path.abspath(__file__), "--config", cfg, "--no-cpu-baseline", "--no-serving",
+               "--steps", str(steps), "--warmup", str(warmup)]
+        log("other workloads: %s" % cfg)
+        try:
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=timeout_s)
+            line = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else ""
+            if r.returncode != 0 or not line:
+                out[cfg] = {"error": "exit status %d" % r.returncode}
+                continue
+            d = json.loads(line)
+        except subprocess.TimeoutExpired:
+            out[cfg] = {"error": "timed out after %d s" % timeout_s}
+            continue
+        except (ValueError, OSError) as e:
+            out[cfg] = {"error": str(e)}
+            continue
+        roof = d["roofline"]
+        e = {"value": d["value"], "unit": d["unit"], "ms_per_step": d["ms_per_step"], "steps": d["steps"],
+             "frac": roof["frac"], "frac_of_measured": roof["frac_of_measured"], "kernel_ms": roof["kernel_ms"],
+             "ops_per_cell": roof["ops_per_cell"], "traffic": roof.get("traffic"), "launch": d["config"]["launch"],
+             "plan": d["config"]["plan"], "workload": d["config"]["workload"],
+             "wide_band_pairs": d["wide_band_pairs"], "deferred_band_pairs": d["deferred_band_pairs"]}
+        if "plain_per_bucket" in d:
+            pl = d["plain_per_bucket"]
+            e["plain_per_bucket"] = {"value": pl["value"], "frac": pl["frac"],
+                                     "bit_exact_vs_persistent": pl["bit_exact_vs_persistent"]}
+            e["persistent_over_plain"] = d["persistent_over_plain"]
+        out[cfg] = e
+    return out
 
 
 if __name__ == "__main__":
