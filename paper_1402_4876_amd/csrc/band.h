@@ -26,11 +26,15 @@
 //
 // Layout.  A band group of 16 lanes (one DPP row) holds two pairs packed in
 // 16-bit halves (one pair with 32-bit values); lane l of strip s holds
-// diagonal delta_lo + 16 s + l, up to 4 strips (64 diagonals).  Right after
-// the fill a wave refills the bands of up to 16 diagonals (one strip); a
-// pair with a wider band gets its score and end cell written and is passed
-// on to a later launch whose items hold only such pairs, so that one wide
-// band does not make the item's other pairs pay for its extra strips.  Row by row:
+// diagonal delta_lo + 16 s + l, up to 4 strips (64 diagonals).  Bands of up
+// to 16 diagonals (one strip) are refilled by the fill kernel itself; a pair
+// with a wider band gets its score and end cell written and is passed on to
+// a later launch whose items hold only such pairs, so that one wide band
+// does not make the item's other pairs pay for its extra strips.  In the
+// 16-lane classes a band of one diagonal that meets row 0 where the
+// alignment may start needs no refill at all (band_route writes it out),
+// and the other narrow bands wait in the wave's pending list until an
+// item's worth of them is refilled at once.  Row by row:
 // the diagonal predecessor is in the lane, the insertion comes from the next
 // diagonal one row up (a DPP shift), and the deletion, which runs along the
 // row across lanes, is a max-plus prefix scan (max over the cells to the
@@ -80,6 +84,124 @@ struct BandLds {
   static constexpr int kEntries = kRows + kBandMaxW;
   static_assert(kRows * 4 + kEntries * 2 <= kGroupWords * 4, "window codes of the widest band fit");
 };
+
+// The pending list of a slot: after the direction-bit (or band record)
+// area and the CIGAR staging of 8 pairs.
+__device__ __forceinline__ MICA_GLOBAL uint32_t* pending_list(const Params* __restrict__ prm, uint8_t* slot) {
+  return (MICA_GLOBAL uint32_t*)(slot + prm->dir_bytes) + (size_t)8 * (size_t)prm->stage_stride;
+}
+
+// Right after a banded fill of 16-lane groups, one lane per pair: the
+// saturated pairs go to the 32-bit re-run, pairs whose band is too wide for
+// the refill to the full traceback, pairs with bands of 17-64 diagonals to
+// the deferred lists of the bucket (score and end cell written now).
+// Outside local mode a band of one diagonal that meets row 0 where the
+// alignment may start (column 0 for an extension) holds no gap: the
+// alignment is that diagonal, written out at once.  Every other pair (score
+// and end cell written now) joins the wave's pending list pend_list[0,
+// *pend), in lane order; the caller refills the list's pairs an item at a
+// time, so that a refill runs on a full item rather than on each fill
+// item's few narrow bands.  The band is the one band_traceback computes.
+template <class V, int P, int R, int MODE>
+__device__ __forceinline__ void band_route(const Params* __restrict__ prm,
+                                           const MICA_GLOBAL uint32_t* __restrict__ gpairs, int npairs,
+                                           const uint32_t* lds, const bool* sat_h, int bucket,
+                                           MICA_GLOBAL uint32_t* pend_list, int* pend) {
+  static_assert(P == 16, "pending lists serve the 16-lane classes");
+  constexpr int NP = V::kPairs;
+  constexpr int PR = P * R;
+  constexpr bool LOCAL = (MODE == 1);
+  constexpr bool EXT = (MODE == 2);
+  constexpr int X = 16 / NP;
+  const int lane = threadIdx.x & 63;
+  const int l = lane & 15;
+  const int h = l / X;
+  const int q = (lane >> 4) * NP + h;
+  const int sa = prm->sa, so = prm->so, se = prm->se;
+  const uint32_t* red = lds + kRedOff;
+  bool join = false;
+  uint32_t pj = 0;
+  if (q < npairs && l == h * X) {
+    bool sat;
+    if constexpr (NP == 2) sat = h ? sat_h[1] : sat_h[0];
+    else sat = sat_h[0];
+    const int p = (int)gpairs[q];
+    if (sat) {  // the 32-bit re-run recomputes the pair
+      const uint32_t pos = atomicAdd(&prm->counters[kCtrRerun], 1u);
+      G(prm->rerun)[pos] = (uint32_t)p;
+    } else {
+      const int m = G(prm->read_len)[p];
+      const int n = G(prm->win_len)[p];
+      const int d0 = EXT ? 0 : PR - m;
+      const int h0 = EXT ? (prm->ext_h0 ? G(prm->ext_h0)[p] : prm->ext_default_h0) : 0;
+      const int scs = (int)red[q * 4 + 0];
+      const int ie = (int)red[q * 4 + 1], je = (int)red[q * 4 + 2];
+      // the band of the traceback (see band_traceback)
+      int W = 0;
+      bool wide = false;
+      if (ie >= 1 && je >= 1) {
+        const int gain = scs + d0 - h0;
+        const int ad = sa * (ie < je ? ie : je) - gain - so;
+        const int ai = sa * ie - gain - so;
+        const int ld = ad >= 0 ? ad / se : 0;
+        const int li = ai >= 0 ? ai / (sa + se) : 0;
+        const int ds = je - ie;
+        int lo = ds - ld, hi = ds + li;
+        lo = lo < -ie ? -ie : lo;
+        hi = hi > je ? je : hi;
+        W = hi - lo + 1;
+        const long hib = EXT ? (long)h0 + (long)sa * (m < n ? m : n) : (long)sa * (m < n ? m : n) - d0;
+        wide = W > kBandMaxW || (NP == 2 && (hib + 16L * se + so > 32767 || 16L * se + so > 32767));
+      }
+      const uint32_t bs = G(prm->bstart)[bucket];
+      if (wide) {  // the full traceback after the fills
+        const uint32_t pos = atomicAdd(&prm->fbcount[bucket], 1u);
+        G(prm->fbsorted)[bs + pos] = (uint32_t)p;
+      } else {
+        G(prm->score)[p] = scs + d0;
+        G(prm->read_end)[p] = ie;
+        G(prm->ref_end)[p] = je;
+        if (!LOCAL && W == 1 && (EXT ? je == ie : je >= ie)) {
+          if (prm->flags & (kOutStart | kOutCigar)) {
+            G(prm->read_start)[p] = 0;
+            G(prm->ref_start)[p] = je - ie;
+          }
+          uint32_t st = 0;
+          if (prm->flags & kOutCigar) {
+            if (prm->cigar_cap >= 1) {
+              G(prm->cigar)[(size_t)p * (size_t)prm->cigar_cap] = (uint32_t)ie << 4;  // ie matches/mismatches
+              G(prm->n_cigar)[p] = 1;
+            } else {
+              st = kStCigarTrunc;
+              G(prm->n_cigar)[p] = -1;
+            }
+          }
+          G(prm->status)[p] = st;
+        } else if (W > kBandInlineW) {
+          // two lists in the bucket's range, so that an item of the later
+          // refill runs the strips its own pairs need: up to 32 diagonals
+          // from the start, wider from the end
+          if (W <= 32) {
+            const uint32_t pos = atomicAdd(&prm->dbcount[bucket], 1u);
+            G(prm->dbsorted)[bs + pos] = (uint32_t)p;
+          } else {
+            const uint32_t pos = atomicAdd(&prm->dbwide[bucket], 1u);
+            G(prm->dbsorted)[bs + G(prm->bcount)[bucket] - 1u - pos] = (uint32_t)p;
+          }
+        } else {
+          join = true;
+          pj = (uint32_t)p;
+        }
+      }
+    }
+  }
+  const uint64_t bal = __ballot(join);
+  if (join) {
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    pend_list[*pend + (int)rank] = pj;
+  }
+  *pend += __builtin_popcountll(bal);
+}
 
 // The banded traceback and the outputs of one work item (all lanes of the
 // wave take part).  red[] holds the fill's result per pair; sat_h[h] whether

@@ -132,10 +132,15 @@ static_assert(kRingWords <= kRedOff, "fill areas below the results");
 constexpr int kWavesPerBlock = 4;
 // widest band of the banded traceback (diagonals); wider pairs are traced
 // back from a full fill of direction bits instead.  Bands up to
-// kBandInlineW diagonals are refilled right after the fill; wider ones by
-// a later launch whose work items hold only such pairs.
+// kBandInlineW diagonals are refilled by the fill kernel (right after the
+// fill, or in the 16-lane classes an item's worth at a time from the wave's
+// pending list); wider ones by a later launch whose work items hold only
+// such pairs.
 constexpr int kBandMaxW = 64;
 constexpr int kBandInlineW = 16;
+// words at the end of a traceback slot that hold a wave's pending pairs
+// (pairs whose band refill waits for an item's worth of them)
+constexpr int kPendWords = 16;
 
 struct Params {
   // batch (device pointers owned by the caller)

@@ -231,14 +231,17 @@ namespace mica {
 // (score-only fill, then the band refill and walk of band.h), full
 // (direction bits of every cell stored during the fill; the fallback for
 // pairs whose band is too wide, and the 32-bit re-run), or the band refill
-// alone of the pairs a banded fill passed on (bands of 17-64 diagonals).
-enum Traceback : int { kTbNone = 0, kTbBand = 1, kTbFull = 2, kTbDefer = 3 };
+// alone of the pairs a banded fill passed on (bands of 17-64 diagonals), or
+// the band refill of a wave's pending pairs (see band_route).
+enum Traceback : int { kTbNone = 0, kTbBand = 1, kTbFull = 2, kTbDefer = 3, kTbPend = 4 };
 
 // One wave-sized work item: G = 64/P groups, each aligning kPairs pairs.
+// pend: the count of the wave's pending list (banded fills of 16-lane
+// classes; unused otherwise).
 template <class V, int P, int R, int MODE, int TB, bool SAT>
 __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
                                           const uint32_t* __restrict__ pairs, int npairs,
-                                          uint32_t* lds, uint8_t* slot, int bucket) {
+                                          uint32_t* lds, uint8_t* slot, int bucket, int* pend = nullptr) {
   typedef typename V::T T;
   constexpr bool DIR = (TB == kTbFull);
   constexpr int NP = V::kPairs;
@@ -260,9 +263,10 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   const MICA_GLOBAL uint32_t* __restrict__ gpairs = G(uni(pairs));
   npairs = uni(npairs);
 
-  if constexpr (TB == kTbDefer) {
+  if constexpr (TB == kTbDefer || TB == kTbPend) {
     // the fill's results (shifted score, i*, j*) come back from the outputs
-    // the banded fill wrote; none of these pairs saturated
+    // the banded fill wrote; none of these pairs saturated.  Pending pairs
+    // (bands of up to 16 diagonals) are refilled as right after a fill.
     uint32_t* red = lds + kRedOff;
     if (lane < npairs) {
       const int p = (int)gpairs[lane];
@@ -275,7 +279,7 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
     bool none[NP];
 #pragma unroll
     for (int h = 0; h < NP; ++h) none[h] = false;
-    band_traceback<V, P, R, MODE, true>(prm, gpairs, npairs, lds, slot, none, bucket);
+    band_traceback<V, P, R, MODE, TB == kTbDefer>(prm, gpairs, npairs, lds, slot, none, bucket);
     return;
   }
 
@@ -707,7 +711,12 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
   }
   lds_wait();
   if constexpr (TB == kTbBand) {
-    band_traceback<V, P, R, MODE, false>(prm, gpairs, npairs, lds, slot, sat_h, bucket);
+    if constexpr (P == 16) {
+      // the caller refills the pending pairs (pending_take)
+      band_route<V, P, R, MODE>(prm, gpairs, npairs, lds, sat_h, bucket, pending_list(prm, slot), pend);
+    } else {
+      band_traceback<V, P, R, MODE, false>(prm, gpairs, npairs, lds, slot, sat_h, bucket);
+    }
     return;
   }
   if constexpr (DIR) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -985,21 +994,21 @@ __device__ __forceinline__ void process_item(const Params* __restrict__ prm,
 
 template <int TB, int CLS, int KIND, int MODE>
 __device__ __forceinline__ void run_one(const Params* prm, const uint32_t* pairs, int np,
-                                        uint32_t* lds, uint8_t* slot, int bucket) {
+                                        uint32_t* lds, uint8_t* slot, int bucket, int* pend = nullptr) {
   constexpr int P = class_lanes(CLS);
   constexpr int R = class_rows(CLS);
   if constexpr (KIND == kK32)
-    process_item<V32, P, R, MODE, TB, false>(prm, pairs, np, lds, slot, bucket);
+    process_item<V32, P, R, MODE, TB, false>(prm, pairs, np, lds, slot, bucket, pend);
   else
-    process_item<V16, P, R, MODE, TB, KIND == kK16Sat>(prm, pairs, np, lds, slot, bucket);
+    process_item<V16, P, R, MODE, TB, KIND == kK16Sat>(prm, pairs, np, lds, slot, bucket, pend);
 }
 
 template <int TB, int MODE, int CLS, int CHI>
 __device__ __forceinline__ void dispatch(int bucket, const Params* prm, const uint32_t* pairs, int np,
-                                         uint32_t* lds, uint8_t* slot) {
+                                         uint32_t* lds, uint8_t* slot, int* pend = nullptr) {
   if constexpr (CLS <= CHI) {
-    if (bucket_class(bucket) == CLS) run_one<TB, CLS, kK16, MODE>(prm, pairs, np, lds, slot, bucket);
-    else dispatch<TB, MODE, CLS + 1, CHI>(bucket, prm, pairs, np, lds, slot);
+    if (bucket_class(bucket) == CLS) run_one<TB, CLS, kK16, MODE>(prm, pairs, np, lds, slot, bucket, pend);
+    else dispatch<TB, MODE, CLS + 1, CHI>(bucket, prm, pairs, np, lds, slot, pend);
   }
 }
 
@@ -1014,6 +1023,31 @@ __device__ __forceinline__ void dispatch_fallback(int bucket, const Params* prm,
 }
 
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// How many of a wave's pending pairs to refill next (at most an item's
+// worth): an item's worth once there are that many, and the rest too when
+// the wave's work ends or moves to another bucket.  Refilled before each
+// fill item, the list never holds more than two items' worth less one
+// (within its kPendWords words).
+__device__ __forceinline__ int pending_take(int pend, int ppi, bool all) {
+  return pend >= ppi ? ppi : (all ? pend : 0);
+}
+// After n of the pending pairs were refilled: the rest to the front.
+__device__ __forceinline__ int pending_drop(MICA_GLOBAL uint32_t* pl, int pend, int n) {
+  const int rest = pend - n;  // <= n: the two ranges do not overlap
+  const int lane = threadIdx.x & 63;
+  if (rest > 0) {
+    uint32_t v = 0;
+    if (lane < rest) v = pl[n + lane];
+    if (lane < rest) pl[lane] = v;
+  }
+  return rest;
+}
+// The pending pairs' stores are read back by the same wave.
+__device__ __forceinline__ void pending_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // Deferred band item idx of a bucket: the items of the pairs with 33-64
 // diagonals first (stored from the end of the bucket's range down), then
@@ -1052,25 +1086,47 @@ k_fill_persistent(const Params* __restrict__ prm) {
   const uint32_t total = G(prm->qstart)[q1];
   // waves beyond the part's item count leave at once (see k_fill_bucket)
   if ((uint32_t)slot_id >= total - base_item) return;
+  // the wave's pending pairs (banded fills) all belong to pend_bucket
+  int pend = 0, pend_bucket = -1;
   for (;;) {
     uint32_t v = 0;
     if (lane == 0) v = atomicAdd(&prm->counters[kCtrQueueHead + QP], 1u);
     const uint32_t item = base_item + wave_uniform(v);
-    if (item >= total) break;
-    // queue position: last q with qstart[q] <= item
-    int lo = q0, hi = q1 - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (G(prm->qstart)[mid] <= item) lo = mid;
-      else hi = mid - 1;
+    const bool done = item >= total;
+    int bucket = -1, np = 0;
+    const uint32_t* pairs = nullptr;
+    if (!done) {
+      // queue position: last q with qstart[q] <= item
+      int lo = q0, hi = q1 - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (G(prm->qstart)[mid] <= item) lo = mid;
+        else hi = mid - 1;
+      }
+      bucket = (int)G(prm->qorder)[lo];
+      const uint32_t idx = item - G(prm->qstart)[lo];
+      const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
+      const uint32_t first = idx * (uint32_t)ppi;
+      const uint32_t cnt = G(prm->bcount)[bucket];
+      np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
+      pairs = prm->sorted + G(prm->bstart)[bucket] + first;
     }
-    const int bucket = (int)G(prm->qorder)[lo];
-    const uint32_t idx = item - G(prm->qstart)[lo];
-    const int ppi = pairs_per_item(bucket_kind(bucket), bucket_class(bucket));
-    const uint32_t first = idx * (uint32_t)ppi;
-    const uint32_t cnt = G(prm->bcount)[bucket];
-    const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    dispatch<TB, MODE, CLO, CHI>(bucket, prm, prm->sorted + G(prm->bstart)[bucket] + first, np, lds, slot);
+    if constexpr (TB == kTbBand) {
+      // the one refill site: an item's worth of pending pairs, and all of
+      // them when the wave moves to another bucket or its work ends (at
+      // most two passes: each takes at least one pair)
+      for (;;) {
+        const int nf = pending_take(pend, 8, done || bucket != pend_bucket);
+        if (nf == 0) break;
+        MICA_GLOBAL uint32_t* pl = pending_list(prm, slot);
+        pending_fence();
+        dispatch<kTbPend, MODE, CLO, CHI>(pend_bucket, prm, (const uint32_t*)pl, nf, lds, slot);
+        pend = pending_drop(pl, pend, nf);
+      }
+      pend_bucket = bucket;
+    }
+    if (done) break;
+    dispatch<TB, MODE, CLO, CHI>(bucket, prm, pairs, np, lds, slot, &pend);
   }
 }
 
@@ -1146,14 +1202,27 @@ __device__ __forceinline__ void drain_list(const Params* __restrict__ prm, const
   constexpr int ppi = pairs_per_item(KIND, CLS);
   const uint32_t items = (cnt + ppi - 1) / ppi;
   if ((uint32_t)slot_id >= items) return;
+  int pend = 0;  // the wave's pending pairs (banded fills of 16-lane classes)
   for (;;) {
     uint32_t v = 0;
     if ((threadIdx.x & 63) == 0) v = atomicAdd(head, 1u);
     const uint32_t it = wave_uniform(v);
+    if constexpr (TB == kTbBand && class_lanes(CLS) == 16) {
+      // one refill site: an item's worth of pending pairs, and at the end
+      // the rest (at most two passes: each takes at least one pair)
+      for (;;) {
+        const int nf = pending_take(pend, ppi, it >= items);
+        if (nf == 0) break;
+        MICA_GLOBAL uint32_t* pl = pending_list(prm, slot);
+        pending_fence();
+        run_one<kTbPend, CLS, KIND, MODE>(prm, (const uint32_t*)pl, nf, lds, slot, bucket);
+        pend = pending_drop(pl, pend, nf);
+      }
+    }
     if (it >= items) break;
     const uint32_t first = it * ppi;
     const int np = (int)((cnt - first) < (uint32_t)ppi ? (cnt - first) : (uint32_t)ppi);
-    run_one<TB, CLS, KIND, MODE>(prm, base + first, np, lds, slot, bucket);
+    run_one<TB, CLS, KIND, MODE>(prm, base + first, np, lds, slot, bucket, &pend);
   }
 }
 

@@ -395,7 +395,8 @@ SlotShape slot_shape(const mica_batch_t* b, uint32_t flags) {
   // band records (two rows per word, 4 strips x 64 lanes), whichever is larger
   sh.dir_bytes = d ? std::max((size_t)(b->max_win_len + 64) * 64 * 16, (size_t)(b->max_read_len / 2 + 1) * 1024) : 0;
   sh.stage_stride = b->max_read_len + b->max_win_len + 2;
-  const size_t stage_bytes = d ? (size_t)8 * sh.stage_stride * 4 : 0;
+  // then a wave's pending pairs (kPendWords words)
+  const size_t stage_bytes = d ? (size_t)8 * sh.stage_stride * 4 + kPendWords * 4 : 0;
   sh.slot_bytes = std::max<size_t>(align_up(sh.dir_bytes + stage_bytes, 256), 256);
   return sh;
 }
