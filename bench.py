@@ -43,10 +43,10 @@ EXT_CLIP = 5  # clipping penalty of the seed-extension workload
 # one SHA-256; for any other build the bench line reports traffic as null.
 MEASURED_TRAFFIC = {
     # config: (build sha256, fetch bytes, write bytes)
-    "c1": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 4280446464, 4077702912),
-    "c2": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 3162552832, 7894188544),
-    "c3": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 14869808256, 10479191744),
-    "ext": ("684ac823a33ada180a303b4f3ecb7099fd4e62c7520efb1cf0ff789fe9edb1bf", 5806509312, 2011122784),
+    "c1": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 3238231168, 2687383424),
+    "c2": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 2924675712, 7233401440),
+    "c3": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 12235160064, 9087330432),
+    "ext": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 3180137216, 1461456064),
     # the search kernel: its own sources (fm_source_sha)
     "bwt": ("7bd545de6e0822eccd77eca98f46c872f8b688666e356e26c45b01fc1e9a9b7b", 12810119168, 26541056),
 }
