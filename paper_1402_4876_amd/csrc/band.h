@@ -85,6 +85,34 @@ struct BandLds {
   static_assert(kRows * 4 + kEntries * 2 <= kGroupWords * 4, "window codes of the widest band fit");
 };
 
+// The band of a pair whose end cell (ie, je) is off row and column 0, from
+// its fill result (shifted score scs, dummy rows d0, anchor score h0): the
+// lowest diagonal, the width (the bounds above), and whether the refill
+// cannot take it: wider than kBandMaxW diagonals, or in packed 16 bits
+// values that could reach the upper clamp (the deletion scan's lane
+// offsets add up to o + 16 e to values up to the pair's bound).
+struct Band {
+  int lo, w;
+  bool wide;
+};
+template <int NP, bool EXT>
+__device__ __forceinline__ Band band_of(const Params* __restrict__ prm, int m, int n, int d0, int h0, int scs, int ie,
+                                        int je) {
+  const int sa = prm->sa, so = prm->so, se = prm->se;
+  const int gain = scs + d0 - h0;  // score gained over the start
+  const int ad = sa * (ie < je ? ie : je) - gain - so;
+  const int ai = sa * ie - gain - so;
+  const int ld = ad >= 0 ? ad / se : 0;
+  const int li = ai >= 0 ? ai / (sa + se) : 0;
+  const int ds = je - ie;
+  int lo = ds - ld, hi = ds + li;
+  lo = lo < -ie ? -ie : lo;
+  hi = hi > je ? je : hi;
+  const long hib = EXT ? (long)h0 + (long)sa * (m < n ? m : n) : (long)sa * (m < n ? m : n) - d0;
+  const int w = hi - lo + 1;
+  return Band{lo, w, w > kBandMaxW || (NP == 2 && (hib + 16L * se + so > 32767 || 16L * se + so > 32767))};
+}
+
 // The pending list of a slot: after the direction-bit (or band record)
 // area and the CIGAR staging of 8 pairs.
 __device__ __forceinline__ MICA_GLOBAL uint32_t* pending_list(const Params* __restrict__ prm, uint8_t* slot) {
@@ -117,7 +145,6 @@ __device__ __forceinline__ void band_route(const Params* __restrict__ prm,
   const int l = lane & 15;
   const int h = l / X;
   const int q = (lane >> 4) * NP + h;
-  const int sa = prm->sa, so = prm->so, se = prm->se;
   const uint32_t* red = lds + kRedOff;
   bool join = false;
   uint32_t pj = 0;
@@ -136,22 +163,13 @@ __device__ __forceinline__ void band_route(const Params* __restrict__ prm,
       const int h0 = EXT ? (prm->ext_h0 ? G(prm->ext_h0)[p] : prm->ext_default_h0) : 0;
       const int scs = (int)red[q * 4 + 0];
       const int ie = (int)red[q * 4 + 1], je = (int)red[q * 4 + 2];
-      // the band of the traceback (see band_traceback)
+      // the band of the traceback
       int W = 0;
       bool wide = false;
       if (ie >= 1 && je >= 1) {
-        const int gain = scs + d0 - h0;
-        const int ad = sa * (ie < je ? ie : je) - gain - so;
-        const int ai = sa * ie - gain - so;
-        const int ld = ad >= 0 ? ad / se : 0;
-        const int li = ai >= 0 ? ai / (sa + se) : 0;
-        const int ds = je - ie;
-        int lo = ds - ld, hi = ds + li;
-        lo = lo < -ie ? -ie : lo;
-        hi = hi > je ? je : hi;
-        W = hi - lo + 1;
-        const long hib = EXT ? (long)h0 + (long)sa * (m < n ? m : n) : (long)sa * (m < n ? m : n) - d0;
-        wide = W > kBandMaxW || (NP == 2 && (hib + 16L * se + so > 32767 || 16L * se + so > 32767));
+        const Band bd = band_of<NP, EXT>(prm, m, n, d0, h0, scs, ie, je);
+        W = bd.w;
+        wide = bd.wide;
       }
       const uint32_t bs = G(prm->bstart)[bucket];
       if (wide) {  // the full traceback after the fills
@@ -257,29 +275,17 @@ __device__ __forceinline__ void band_traceback(const Params* __restrict__ prm,
       je[h] = (int)red[q * 4 + 2];
       sat[h] = sat_h[h];
       if (!sat[h] && ie[h] >= 1 && je[h] >= 1) {
-        const int gain = scs[h] + d0[h] - h0[h];  // score gained over the start
-        const int ad = sa * (ie[h] < je[h] ? ie[h] : je[h]) - gain - so;
-        const int ai = sa * ie[h] - gain - so;
-        const int ld = ad >= 0 ? ad / se : 0;
-        const int li = ai >= 0 ? ai / (sa + se) : 0;
-        const int ds = je[h] - ie[h];
-        int lo = ds - ld, hi = ds + li;
-        lo = lo < -ie[h] ? -ie[h] : lo;
-        hi = hi > je[h] ? je[h] : hi;
-        dlo[h] = lo;
-        W[h] = hi - lo + 1;
-        // 16-bit: the scan's lane offsets (up to o + 16 e) must not reach
-        // the upper clamp from values up to the pair's bound
-        const long hib = EXT ? (long)h0[h] + (long)sa * (mm[h] < nn[h] ? mm[h] : nn[h])
-                             : (long)sa * (mm[h] < nn[h] ? mm[h] : nn[h]) - d0[h];
-        fb[h] = W[h] > kBandMaxW || (NP == 2 && (hib + 16L * se + so > 32767 || 16L * se + so > 32767));
+        const Band bd = band_of<NP, EXT>(prm, mm[h], nn[h], d0[h], h0[h], scs[h], ie[h], je[h]);
+        dlo[h] = bd.lo;
+        W[h] = bd.w;
+        fb[h] = bd.wide;
         dfr[h] = !DEFER && !fb[h] && W[h] > kBandInlineW;
         act[h] = !fb[h] && !dfr[h];
         if (act[h]) {
           rows_l = ie[h] > rows_l ? ie[h] : rows_l;
           const int ns = (W[h] + 15) >> 4;
           ns_l = ns > ns_l ? ns : ns_l;
-          mr_l = -lo > mr_l ? -lo : mr_l;
+          mr_l = -bd.lo > mr_l ? -bd.lo : mr_l;
         }
       }
     }
