@@ -43,10 +43,10 @@ EXT_CLIP = 5  # clipping penalty of the seed-extension workload
 # one SHA-256; for any other build the bench line reports traffic as null.
 MEASURED_TRAFFIC = {
     # config: (build sha256, fetch bytes, write bytes)
-    "c1": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 3238231168, 2687383424),
-    "c2": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 2924675712, 7233401440),
-    "c3": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 12235160064, 9087330432),
-    "ext": ("b2d59734c5fb1fef1b6db0d769ad6d0dee196a078e6476bb9993ca8fd6d41cc3", 3180137216, 1461456064),
+    "c1": ("bab58b60f45863bf65ef5a187a5b215fe18b78cfb97aa35d468bd8a7b3c23846", 3229168128, 2685101696),
+    "c2": ("bab58b60f45863bf65ef5a187a5b215fe18b78cfb97aa35d468bd8a7b3c23846", 3101558400, 7240992096),
+    "c3": ("bab58b60f45863bf65ef5a187a5b215fe18b78cfb97aa35d468bd8a7b3c23846", 11805670912, 9037802912),
+    "ext": ("bab58b60f45863bf65ef5a187a5b215fe18b78cfb97aa35d468bd8a7b3c23846", 3151174912, 1461079552),
     # the search kernel: its own sources (fm_source_sha)
     "bwt": ("7bd545de6e0822eccd77eca98f46c872f8b688666e356e26c45b01fc1e9a9b7b", 12810119168, 26541056),
 }
